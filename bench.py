@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the 2-D DWT hot path on one MI355X.
+
+A step is one forward plus one inverse L-level transform of one image that is
+already resident in HBM. The default workload is the headline one: a
+4096 x 4096 FP32 image (sum of random sinusoids plus noise), CDF 9/7, five
+levels, non-separable lifting. Steps rotate over several buffer sets whose
+total size exceeds the 256 MB Infinity Cache, so each step reads its input
+from HBM rather than from the cache.
+
+Prints one JSON line with the throughput in Gpixel/s (original-image pixels
+per second of forward+inverse), the roofline of the dominant kernel
+(level-1 launch, HBM-bound), the separable-lifting kernel measured the same
+way, and the FP64 oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("Gpixel/s fwd+inv CDF 9/7 DWT at 4096², 5 levels (% HBM peak); "
+          "serving p50/p99")
+KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp")
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1705_08266_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def level_bytes(W, H, levels, es_store):
+    """Algorithmic HBM bytes of each forward level launch (the inverse level is
+    symmetric): read the level input once, write its four bands once. The
+    user-visible image and bands use the storage size; intermediate LL is FP32."""
+    out = []
+    for j in range(1, levels + 1):
+        w, h = W >> (j - 1), H >> (j - 1)
+        px = w * h
+        in_es = es_store if j == 1 else 4
+        ll_es = es_store if j == levels else 4
+        out.append(px * in_es + (px // 4) * (3 * es_store + ll_es))
+    return out
+
+
+def make_image(W, H, kind, seed):
+    import synthetic
+    if kind == "sinusoid":
+        return synthetic.sinusoid_image(H, W, seed=seed)
+    return synthetic.uniform_image(H, W, seed=seed)
+
+
+def run_gpu(args, x_np, scheme):
+    import torch
+    import paper_1705_08266_amd as dwt
+
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    H, W = x_np.shape
+    L = args.levels
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(x_np).to(dev).to(tdt)
+    sets = []
+    for s in range(args.sets):
+        src = x0.clone()
+        coef = torch.empty_like(src)
+        rec = torch.empty_like(src)
+        ws = dwt.make_workspace(W, H, L, dev)
+        sets.append((src, coef, rec, ws))
+    stream = torch.cuda.current_stream()
+
+    def step(k, ev_f=None, ev_i=None):
+        src, coef, rec, ws = sets[k % len(sets)]
+        dwt.forward(src, args.wavelet, L, scheme, out=coef, workspace=ws, events=ev_f)
+        dwt.inverse(coef, args.wavelet, L, scheme, out=rec, workspace=ws, events=ev_i)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [([torch.cuda.Event(enable_timing=True) for _ in range(2 * L)],
+            [torch.cuda.Event(enable_timing=True) for _ in range(2 * L)]) for _ in range(K)]
+    for ef, ei in evs:              # materialise the events before timing
+        for e in ef + ei:
+            e.record(stream)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(K):
+        step(k, evs[k][0], evs[k][1])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = t_start.elapsed_time(t_end)
+
+    fwd_ms = [0.0] * L
+    inv_ms = [0.0] * L
+    for ef, ei in evs:
+        for j in range(L):
+            fwd_ms[j] += ef[2 * j].elapsed_time(ef[2 * j + 1]) / K
+            inv_ms[j] += ei[2 * j].elapsed_time(ei[2 * j + 1]) / K
+
+    # parity of what was timed: set 0's coefficients and reconstruction
+    src, coef, rec, _ = sets[0]
+    out = dict(total_ms=total_ms, wall_s=wall, fwd_level_ms=fwd_ms, inv_level_ms=inv_ms,
+               coef=coef.float().cpu().numpy(), rec=rec.float().cpu().numpy(),
+               stored=src.float().cpu().numpy())
+    del sets
+    torch.cuda.empty_cache()
+    return out
+
+
+def load_traffic(kernel_key: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(x64, wavelet, levels, seconds):
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    oracle.forward(x64[:64, :64].copy(), wavelet, 1, nthreads=threads)  # load/build
+    reps, t0, coef = 0, time.perf_counter(), None
+    while True:
+        coef = oracle.forward(x64, wavelet, levels, nthreads=threads)
+        oracle.inverse(coef, wavelet, levels, nthreads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    H, W = x64.shape
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=W * H * reps / el / 1e9, unit="Gpixel/s", cores=threads,
+                kind="oracle",
+                sample=(f"{reps} x (forward + inverse) of the same {W}x{H} image, "
+                        f"{wavelet}, {levels} levels, FP64, OpenMP over rows/columns, "
+                        f"{el:.1f} s; host CPU: {cpu_model}")), coef
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--size", default="4096x4096", help="WIDTHxHEIGHT")
+    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--wavelet", default="cdf97", choices=["cdf97", "cdf53"])
+    ap.add_argument("--scheme", default="nonseparable", choices=["nonseparable", "separable"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--image", default="sinusoid", choices=["sinusoid", "uniform"])
+    ap.add_argument("--sets", type=int, default=4,
+                    help="rotating buffer sets (4 x 4096^2 x 3 FP32 > 256 MB cache)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-separable", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the transform of one image is not sharded "
+              "across GPUs in this build (see DESIGN.md for how it would shard). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import synthetic
+
+    W, H = (int(v) for v in args.size.lower().split("x"))
+    L = args.levels
+    x = make_image(W, H, args.image, synthetic.SEED_BASE + 2)
+    print(f"[bench] {W}x{H} {args.image} {args.dtype} {args.wavelet} L={L} "
+          f"{args.scheme}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+          flush=True)
+    main_run = run_gpu(args, x, args.scheme)
+    sep_run = None
+    if not args.no_separable and args.scheme != "separable":
+        print("[bench] separable-lifting kernel, same protocol", file=sys.stderr, flush=True)
+        sep_run = run_gpu(args, x, "separable")
+
+    es = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
+    lb = level_bytes(W, H, L, es)
+    K = args.steps
+    ms_step = main_run["total_ms"] / K
+    gpx = W * H / (ms_step * 1e-3) / 1e9
+    alg_bytes_step = 2 * sum(lb)
+
+    f1, i1 = main_run["fwd_level_ms"][0], main_run["inv_level_ms"][0]
+    dom = "inverse" if i1 > f1 else "forward"
+    dom_ms = max(f1, i1)
+    achieved = lb[0] / (dom_ms * 1e-3) / 1e9
+    kernel_key = f"{dom}_level1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(kernel_key),
+                    kernel=f"{dom} level 1 ({args.scheme})",
+                    bytes_per_launch=lb[0], avg_launch_ms=round(dom_ms, 5))
+
+    result = dict(
+        metric=METRIC, value=round(gpx, 3), unit="Gpixel/s", n_gpus=1, steps=K,
+        warmup=args.warmup, ms_per_step=round(ms_step, 5), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype=args.dtype, data="synthetic",
+        config=dict(workload=(f"{W}x{H} {args.image} image, {args.dtype} storage, "
+                              f"{args.wavelet} forward+inverse, {L} levels, "
+                              f"{args.scheme} lifting, {args.sets} rotating buffer sets"),
+                    width=W, height=H, levels=L, wavelet=args.wavelet, scheme=args.scheme,
+                    storage=args.dtype, buffer_sets=args.sets),
+        roofline=roofline,
+        hbm_frac_whole_step=round(alg_bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        algorithmic_bytes_per_step=alg_bytes_step,
+        level_ms=dict(forward=[round(v, 5) for v in main_run["fwd_level_ms"]],
+                      inverse=[round(v, 5) for v in main_run["inv_level_ms"]]),
+    )
+    if sep_run is not None:
+        s_ms = sep_run["total_ms"] / K
+        s1 = max(sep_run["fwd_level_ms"][0], sep_run["inv_level_ms"][0])
+        result["separable"] = dict(
+            value=round(W * H / (s_ms * 1e-3) / 1e9, 3), ms_per_step=round(s_ms, 5),
+            level1_gbs=round(lb[0] / (s1 * 1e-3) / 1e9, 1),
+            level_ms=dict(forward=[round(v, 5) for v in sep_run["fwd_level_ms"]],
+                          inverse=[round(v, 5) for v in sep_run["inv_level_ms"]]))
+
+    x_stored = main_run["stored"].astype(np.float64)
+    scale = float(np.abs(x_stored).max())
+    if not args.no_cpu_baseline:
+        print(f"[bench] oracle on host cores, ~{args.cpu_seconds:.0f} s", file=sys.stderr,
+              flush=True)
+        cb, ref = cpu_baseline(x_stored, args.wavelet, L, args.cpu_seconds)
+        result["cpu_baseline"] = cb
+        result["max_err_rel"] = dict(
+            forward=float(np.abs(main_run["coef"] - ref).max() / scale),
+            round_trip=float(np.abs(main_run["rec"] - x_stored).max() / scale))
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

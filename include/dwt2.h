@@ -1,0 +1,171 @@
+/*
+ * dwt2.h - 2-D discrete wavelet transform on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the single-scale and multi-level 2-D CDF 9/7 and
+ * CDF 5/3 forward and inverse DWT with the non-separable lifting scheme of
+ * Barina, Kula, Matysek and Zemcik, "Accelerating Discrete Wavelet
+ * Transforms on GPUs": each horizontal and vertical predict (update) pair of
+ * the separable lifting scheme is merged into one spatial step T_P (S_U) on a
+ * 2x2 polyphase quad (Sec. 3), with the constant parts P0, U0 split off and
+ * applied to the unit's own quad without a barrier (Sec. 3, "optimization").
+ * The separable lifting scheme (Sec. 2) is available as a baseline.
+ *
+ * Problem statement (Sec. 2): the 2-D transform splits the image into a
+ * quadruple of coefficient bands per level. Conventions, where the paper is
+ * silent:
+ *   - pixel (0,0) is an even/even sample; quad (i,j) holds
+ *     a = x[2j][2i] -> LL, b = x[2j][2i+1] -> HL, c = x[2j+1][2i] -> LH,
+ *     d = x[2j+1][2i+1] -> HH;
+ *   - boundary: whole-sample symmetric extension (x[-k] = x[k],
+ *     x[N-1+k] = x[N-1-k]), periodic with period 2N-2, so any N >= 2 works;
+ *   - scaling: unit gain (low-pass DC gain 1, high-pass Nyquist gain 1);
+ *   - multi-level: dyadic recursion on LL, written in the Mallat layout
+ *     inside one W x H coefficient buffer: after level j, LL_j is the
+ *     (W/2^j) x (H/2^j) top-left block, HL_j is to its right, LH_j below it
+ *     and HH_j diagonally below-right.
+ *
+ * Arithmetic is FP32. Storage of the image and the coefficients may be FP32,
+ * FP16 or BF16; intermediate low-low bands between levels stay FP32 in the
+ * caller's workspace.
+ *
+ * Memory and threading
+ *   - All buffer pointers are DEVICE pointers on the current HIP device.
+ *   - The caller owns every buffer. The library allocates and frees no device
+ *     memory, keeps no global mutable state except a thread-local last HIP
+ *     error, and never synchronises: every call enqueues work on `stream`
+ *     (a hipStream_t; NULL = the default stream) and returns.
+ *   - Argument errors are detected before anything is enqueued. Faults during
+ *     execution surface at the caller's next synchronisation of `stream`.
+ *   - Calls on different streams that use disjoint buffers may overlap.
+ */
+#ifndef DWT2_H
+#define DWT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point that can fail. */
+typedef enum {
+    DWT2_OK = 0,
+    DWT2_ERR_INVALID_ARG = -1,  /* null pointer, bad size, overlap, mismatch */
+    DWT2_ERR_UNSUPPORTED = -2,  /* unknown enum value or tile id */
+    DWT2_ERR_WORKSPACE = -3,    /* workspace smaller than required */
+    DWT2_ERR_HIP = -4           /* a HIP launch failed; see dwt2_last_hip_error */
+} dwt2_status;
+
+typedef enum { DWT2_CDF97 = 0, DWT2_CDF53 = 1 } dwt2_wavelet;
+
+/* Only whole-sample symmetric extension is defined. */
+typedef enum { DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC = 0 } dwt2_boundary;
+
+/* Storage type of a buffer; arithmetic is always FP32. */
+typedef enum { DWT2_F32 = 0, DWT2_F16 = 1, DWT2_BF16 = 2 } dwt2_dtype;
+
+/* NONSEPARABLE: merged spatial steps S_U | T_P per lifting pair (Sec. 3).
+ * SEPARABLE: S_U^V | S_U^H | T_P^V | T_P^H per lifting pair (Sec. 2). */
+typedef enum { DWT2_NONSEPARABLE = 0, DWT2_SEPARABLE = 1 } dwt2_scheme;
+
+/* A 2-D buffer: `height` rows of `width` elements, row starts `pitch`
+ * elements apart (pitch >= width), elements of type `dtype`. */
+typedef struct {
+    int32_t width;
+    int32_t height;
+    int64_t pitch;
+    int32_t dtype;
+} dwt2_desc;
+
+/* Bytes of FP32 workspace that an L-level transform of a width x height
+ * image needs: (W/2)(H/2) floats for L >= 2, plus (W/4)(H/4) for L >= 3.
+ * Returns 0 for L = 1 and for invalid sizes. */
+size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels);
+
+/* Forward L-level 2-D DWT.
+ *   src   : the image, described by *src_d (read only).
+ *   coef  : the Mallat-layout coefficients, described by *coef_d; same width,
+ *           height and dtype as the image. Must not overlap src.
+ *   wavelet, boundary, scheme : enum values above.
+ *   levels: 1..16; width and height must be divisible by 2^levels.
+ *   tiles : NULL to let the library choose, else `levels` tile ids
+ *           (0 <= id < dwt2_tile_config_count()), one per level.
+ *   workspace, workspace_bytes : FP32 scratch of at least
+ *           dwt2_workspace_bytes(width, height, levels) bytes; may be NULL
+ *           when that is 0. Must not overlap src or coef.
+ *   level_events : NULL, or 2*levels hipEvent_t handles; events
+ *           [2j] and [2j+1] are recorded on `stream` before and after the
+ *           launch of level j+1, for per-kernel timing.
+ *   stream: hipStream_t to enqueue on.
+ * Returns a dwt2_status. */
+int dwt2_forward(const void *src, const dwt2_desc *src_d,
+                 void *coef, const dwt2_desc *coef_d,
+                 int32_t wavelet, int32_t levels, int32_t boundary,
+                 int32_t scheme, const int32_t *tiles,
+                 void *workspace, size_t workspace_bytes,
+                 void *const *level_events, void *stream);
+
+/* Inverse L-level 2-D DWT: coef (Mallat layout, read only) -> dst.
+ * Arguments as for dwt2_forward; tiles[j] and level_events[2j], [2j+1]
+ * belong to level j+1 (processed last to first). */
+int dwt2_inverse(const void *coef, const dwt2_desc *coef_d,
+                 void *dst, const dwt2_desc *dst_d,
+                 int32_t wavelet, int32_t levels, int32_t boundary,
+                 int32_t scheme, const int32_t *tiles,
+                 void *workspace, size_t workspace_bytes,
+                 void *const *level_events, void *stream);
+
+/* One forward level, one kernel launch (the building block of dwt2_forward).
+ *   in    : level input, width x height (both even), pitch in_pitch, in_dtype.
+ *   ll    : (width/2) x (height/2) low-low output, pitch ll_pitch, ll_dtype.
+ *   hl, lh, hh : the three detail bands, each (width/2) x (height/2), sharing
+ *           pitch band_pitch and band_dtype.
+ * No output may overlap the input. */
+int dwt2_forward_level(const void *in, int64_t in_pitch, int32_t in_dtype,
+                       int32_t width, int32_t height,
+                       void *ll, int64_t ll_pitch, int32_t ll_dtype,
+                       void *hl, void *lh, void *hh, int64_t band_pitch,
+                       int32_t band_dtype,
+                       int32_t wavelet, int32_t scheme, int32_t tile,
+                       void *stream);
+
+/* One inverse level: four bands of (width/2) x (height/2) -> out
+ * (width x height). `tile` < 0 lets the library choose. */
+int dwt2_inverse_level(const void *ll, int64_t ll_pitch, int32_t ll_dtype,
+                       const void *hl, const void *lh, const void *hh,
+                       int64_t band_pitch, int32_t band_dtype,
+                       void *out, int64_t out_pitch, int32_t out_dtype,
+                       int32_t width, int32_t height,
+                       int32_t wavelet, int32_t scheme, int32_t tile,
+                       void *stream);
+
+/* Tile configurations compiled into the library. A tile is a workgroup of
+ * `waves` wavefronts stacked vertically; each lane owns `quads_per_lane`
+ * consecutive quads of a row and `rows_per_wave` quad rows. Of the
+ * (64*quads_per_lane) x (waves*rows_per_wave) quad window, the centre
+ * out_x x out_y quads are written; the rest is the lifting halo.
+ * Returns DWT2_OK or DWT2_ERR_UNSUPPORTED; null out-pointers are skipped. */
+int dwt2_tile_config_count(void);
+int dwt2_tile_config_info(int32_t tile, int32_t wavelet,
+                          int32_t *quads_per_lane, int32_t *rows_per_wave,
+                          int32_t *waves, int32_t *out_x, int32_t *out_y);
+
+/* The tile id the library picks for one level of the given size. */
+int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet,
+                      int32_t scheme, int32_t dtype);
+
+/* Human-readable text of a status code (static storage). */
+const char *dwt2_status_string(int status);
+
+/* hipError_t behind the most recent DWT2_ERR_HIP on this thread. */
+int dwt2_last_hip_error(void);
+
+/* Library ABI version (major*100 + minor). */
+int dwt2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWT2_H */

@@ -1,0 +1,84 @@
+"""ctypes declarations of the C ABI in include/dwt2.h.
+
+The library is loaded from this package directory only. If it is missing the
+load fails loudly: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdwt2.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
+CDF97, CDF53 = 0, 1
+EXT_WHOLE_SAMPLE_SYMMETRIC = 0
+F32, F16, BF16 = 0, 1, 2
+NONSEPARABLE, SEPARABLE = 0, 1
+
+# Every function declared in include/dwt2.h: name -> (restype, argtypes)
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_ip32 = ctypes.POINTER(ctypes.c_int32)
+
+
+class Desc(ctypes.Structure):
+    """dwt2_desc."""
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("pitch", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+_DescP = ctypes.POINTER(Desc)
+
+SIGNATURES = {
+    "dwt2_workspace_bytes": (_sz, [_i32, _i32, _i32]),
+    "dwt2_forward": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
+                                    _ip32, _vp, _sz, _vp, _vp]),
+    "dwt2_inverse": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
+                                    _ip32, _vp, _sz, _vp, _vp]),
+    "dwt2_forward_level": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _i64, _i32,
+                                          _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp]),
+    "dwt2_inverse_level": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _i32,
+                                          _vp, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _vp]),
+    "dwt2_tile_config_count": (ctypes.c_int, []),
+    "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32]),
+    "dwt2_default_tile": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
+    "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dwt2_last_hip_error": (ctypes.c_int, []),
+    "dwt2_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+class DWT2Error(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        text = load().dwt2_status_string(status).decode()
+        extra = ""
+        if status == ERR_HIP:
+            extra = f" (hipError_t {load().dwt2_last_hip_error()})"
+        super().__init__(f"{what}: {text}{extra}" if what else text + extra)
+
+
+def load():
+    """Load libdwt2.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run paper_1705_08266_amd.build.build() "
+            "(hipcc --offload-arch=gfx950). There is no fallback path.")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str = ""):
+    if status != OK:
+        raise DWT2Error(status, what)

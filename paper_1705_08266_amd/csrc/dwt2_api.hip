@@ -1,0 +1,337 @@
+// C ABI of the 2-D DWT library: argument checking, level planning, launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "dwt2.h"
+#include "dwt2_table.hpp"
+
+namespace {
+
+using namespace dwt2;
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    return DWT2_ERR_HIP;
+}
+
+size_t elem_size(int dt) { return dt == DWT2_F32 ? 4 : 2; }
+bool valid_dtype(int dt) { return dt == DWT2_F32 || dt == DWT2_F16 || dt == DWT2_BF16; }
+bool valid_wavelet(int w) { return w == DWT2_CDF97 || w == DWT2_CDF53; }
+bool valid_scheme(int s) { return s == DWT2_NONSEPARABLE || s == DWT2_SEPARABLE; }
+
+// Byte span [lo, hi) touched by a rows x cols buffer.
+struct Span {
+    uintptr_t lo, hi;
+};
+Span span_of(const void *p, int64_t rows, int64_t cols, int64_t pitch, int dt) {
+    const uintptr_t lo = (uintptr_t)p;
+    const uint64_t n = rows > 0 ? (uint64_t)((rows - 1) * pitch + cols) : 0;
+    return {lo, lo + n * elem_size(dt)};
+}
+bool overlaps(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+
+bool aligned(const void *p, int64_t pitch, int dt, int vec_elems) {
+    size_t bytes = (size_t)vec_elems * elem_size(dt);
+    if (bytes > 16) bytes = 16;
+    return ((uintptr_t)p % bytes) == 0 && ((size_t)pitch * elem_size(dt)) % bytes == 0;
+}
+
+int out_x(int tile, int) { return 64 * kTiles[tile].qpl - 2 * kTiles[tile].qpl; }
+int out_y(int tile, int wavelet) {
+    const int np = wavelet == DWT2_CDF97 ? 2 : 1;
+    return kTiles[tile].waves * kTiles[tile].rows - 2 * np;
+}
+int grid_of(int tile, int wavelet, int nqx, int nqy, int *tx, int *ty) {
+    const int ox = out_x(tile, wavelet), oy = out_y(tile, wavelet);
+    *tx = (nqx + ox - 1) / ox;
+    *ty = (nqy + oy - 1) / oy;
+    return *tx * *ty;
+}
+
+// Tile choice for one level: the tallest window that still gives the chip
+// enough workgroups; small levels fall back to small windows.
+int pick_tile(int width, int height, int wavelet) {
+    static const int order[] = {0, 7, 1};
+    const int nqx = width / 2, nqy = height / 2;
+    int best = order[0], best_grid = 0;
+    for (int t : order) {
+        int tx, ty;
+        const int g = grid_of(t, wavelet, nqx, nqy, &tx, &ty);
+        if (g >= 512) return t;
+        if (g > best_grid) { best = t; best_grid = g; }
+    }
+    return best;
+}
+
+const FwdTable &fwd_table(int dt) {
+    return dt == DWT2_F32 ? kFwdF32 : dt == DWT2_F16 ? kFwdF16 : kFwdBF16;
+}
+const InvTable &inv_table(int dt) {
+    return dt == DWT2_F32 ? kInvF32 : dt == DWT2_F16 ? kInvF16 : kInvBF16;
+}
+
+int check_level_dims(int32_t width, int32_t height) {
+    if (width < 2 || height < 2 || (width & 1) || (height & 1)) return DWT2_ERR_INVALID_ARG;
+    return DWT2_OK;
+}
+
+int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height,
+              void *ll, int64_t ll_pitch, int ll_dt, void *hl, void *lh, void *hh,
+              int64_t band_pitch, int band_dt, int wavelet, int scheme, int tile,
+              hipStream_t stream) {
+    const int nqx = width / 2, nqy = height / 2;
+    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    FwdParams p;
+    p.in = in; p.in_pitch = in_pitch;
+    p.ll = ll; p.ll_pitch = ll_pitch;
+    p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
+    p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
+    const int grid = grid_of(tile, wavelet, nqx, nqy, &p.tiles_x, &p.tiles_y);
+    const int q = kTiles[tile].qpl;
+    p.vec_in = aligned(in, in_pitch, in_dt, 2 * q);
+    p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
+    p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
+                 aligned(hh, band_pitch, band_dt, q);
+    const FwdLauncher f =
+        fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
+    const hipError_t e = f(p, grid, stream);
+    return e == hipSuccess ? DWT2_OK : hip_fail(e);
+}
+
+int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const void *lh,
+              const void *hh, int64_t band_pitch, int band_dt, void *out, int64_t out_pitch,
+              int out_dt, int width, int height, int wavelet, int scheme, int tile,
+              hipStream_t stream) {
+    const int nqx = width / 2, nqy = height / 2;
+    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    InvParams p;
+    p.ll = ll; p.ll_pitch = ll_pitch;
+    p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
+    p.out = out; p.out_pitch = out_pitch;
+    p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
+    const int grid = grid_of(tile, wavelet, nqx, nqy, &p.tiles_x, &p.tiles_y);
+    const int q = kTiles[tile].qpl;
+    p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
+    p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
+                 aligned(hh, band_pitch, band_dt, q);
+    p.vec_out = aligned(out, out_pitch, out_dt, 2 * q);
+    const InvLauncher f =
+        inv_table(band_dt)[wavelet][scheme][ll_dt == DWT2_F32][out_dt == DWT2_F32][tile];
+    const hipError_t e = f(p, grid, stream);
+    return e == hipSuccess ? DWT2_OK : hip_fail(e);
+}
+
+// Checks shared by the one-level entry points. `a` is the full-resolution
+// buffer (input of the forward, output of the inverse).
+int check_level_args(const void *a, int64_t a_pitch, int a_dt, int32_t width, int32_t height,
+                     const void *ll, int64_t ll_pitch, int ll_dt, const void *hl,
+                     const void *lh, const void *hh, int64_t band_pitch, int band_dt,
+                     int32_t wavelet, int32_t scheme, int32_t tile) {
+    if (!a || !ll || !hl || !lh || !hh) return DWT2_ERR_INVALID_ARG;
+    if (check_level_dims(width, height)) return DWT2_ERR_INVALID_ARG;
+    if (!valid_dtype(a_dt) || !valid_dtype(ll_dt) || !valid_dtype(band_dt) ||
+        !valid_wavelet(wavelet) || !valid_scheme(scheme))
+        return DWT2_ERR_UNSUPPORTED;
+    if (tile >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+    // The full-resolution and LL buffers are either FP32 or the band type.
+    if ((a_dt != band_dt && a_dt != DWT2_F32) || (ll_dt != band_dt && ll_dt != DWT2_F32))
+        return DWT2_ERR_INVALID_ARG;
+    const int nqx = width / 2, nqy = height / 2;
+    if (a_pitch < width || ll_pitch < nqx || band_pitch < nqx) return DWT2_ERR_INVALID_ARG;
+    const Span sa = span_of(a, height, width, a_pitch, a_dt);
+    const Span sl = span_of(ll, nqy, nqx, ll_pitch, ll_dt);
+    const Span s1 = span_of(hl, nqy, nqx, band_pitch, band_dt);
+    const Span s2 = span_of(lh, nqy, nqx, band_pitch, band_dt);
+    const Span s3 = span_of(hh, nqy, nqx, band_pitch, band_dt);
+    if (overlaps(sa, sl) || overlaps(sa, s1) || overlaps(sa, s2) || overlaps(sa, s3))
+        return DWT2_ERR_INVALID_ARG;
+    return DWT2_OK;
+}
+
+// Checks shared by the multi-level entry points.
+int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_desc *yd,
+                int32_t wavelet, int32_t levels, int32_t boundary, int32_t scheme,
+                const int32_t *tiles, const void *ws, size_t ws_bytes) {
+    if (!x || !xd || !y || !yd) return DWT2_ERR_INVALID_ARG;
+    if (!valid_wavelet(wavelet) || !valid_scheme(scheme) ||
+        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC || !valid_dtype(xd->dtype) ||
+        !valid_dtype(yd->dtype))
+        return DWT2_ERR_UNSUPPORTED;
+    if (levels < 1 || levels > 16) return DWT2_ERR_INVALID_ARG;
+    const int32_t W = xd->width, H = xd->height;
+    if (yd->width != W || yd->height != H || yd->dtype != xd->dtype) return DWT2_ERR_INVALID_ARG;
+    if (W < 2 || H < 2) return DWT2_ERR_INVALID_ARG;
+    if ((W % (1 << levels)) != 0 || (H % (1 << levels)) != 0) return DWT2_ERR_INVALID_ARG;
+    if (xd->pitch < W || yd->pitch < W) return DWT2_ERR_INVALID_ARG;
+    if (tiles) {
+        for (int j = 0; j < levels; ++j)
+            if (tiles[j] < -1 || tiles[j] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+    }
+    const Span sx = span_of(x, H, W, xd->pitch, xd->dtype);
+    const Span sy = span_of(y, H, W, yd->pitch, yd->dtype);
+    if (overlaps(sx, sy)) return DWT2_ERR_INVALID_ARG;
+    const size_t need = dwt2_workspace_bytes(W, H, levels);
+    if (need > 0) {
+        if (!ws || ws_bytes < need) return DWT2_ERR_WORKSPACE;
+        const Span sw{(uintptr_t)ws, (uintptr_t)ws + need};
+        if (overlaps(sw, sx) || overlaps(sw, sy)) return DWT2_ERR_INVALID_ARG;
+    }
+    return DWT2_OK;
+}
+
+int record(void *const *events, int idx, hipStream_t s) {
+    if (!events) return DWT2_OK;
+    const hipError_t e = hipEventRecord((hipEvent_t)events[idx], s);
+    return e == hipSuccess ? DWT2_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dwt2_version(void) { return 100; }
+
+const char *dwt2_status_string(int status) {
+    switch (status) {
+        case DWT2_OK: return "ok";
+        case DWT2_ERR_INVALID_ARG: return "invalid argument";
+        case DWT2_ERR_UNSUPPORTED: return "unsupported wavelet, scheme, boundary, dtype or tile";
+        case DWT2_ERR_WORKSPACE: return "workspace too small";
+        case DWT2_ERR_HIP: return "HIP launch failed";
+        default: return "unknown status";
+    }
+}
+
+int dwt2_last_hip_error(void) { return g_last_hip_error; }
+
+size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels) {
+    if (width < 2 || height < 2 || levels < 1 || levels > 16) return 0;
+    if ((width % (1 << levels)) != 0 || (height % (1 << levels)) != 0) return 0;
+    if (levels == 1) return 0;
+    size_t n = (size_t)(width / 2) * (size_t)(height / 2);
+    if (levels >= 3) n += (size_t)(width / 4) * (size_t)(height / 4);
+    return n * sizeof(float);
+}
+
+int dwt2_tile_config_count(void) { return kNumTiles; }
+
+int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *quads_per_lane,
+                          int32_t *rows_per_wave, int32_t *waves, int32_t *ox, int32_t *oy) {
+    if (tile < 0 || tile >= kNumTiles || !valid_wavelet(wavelet)) return DWT2_ERR_UNSUPPORTED;
+    if (quads_per_lane) *quads_per_lane = kTiles[tile].qpl;
+    if (rows_per_wave) *rows_per_wave = kTiles[tile].rows;
+    if (waves) *waves = kTiles[tile].waves;
+    if (ox) *ox = out_x(tile, wavelet);
+    if (oy) *oy = out_y(tile, wavelet);
+    return DWT2_OK;
+}
+
+int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet, int32_t scheme,
+                      int32_t dtype) {
+    (void)scheme; (void)dtype;
+    if (check_level_dims(width, height) || !valid_wavelet(wavelet)) return DWT2_ERR_INVALID_ARG;
+    return pick_tile(width, height, wavelet);
+}
+
+int dwt2_forward_level(const void *in, int64_t in_pitch, int32_t in_dtype, int32_t width,
+                       int32_t height, void *ll, int64_t ll_pitch, int32_t ll_dtype, void *hl,
+                       void *lh, void *hh, int64_t band_pitch, int32_t band_dtype,
+                       int32_t wavelet, int32_t scheme, int32_t tile, void *stream) {
+    const int st = check_level_args(in, in_pitch, in_dtype, width, height, ll, ll_pitch,
+                                    ll_dtype, hl, lh, hh, band_pitch, band_dtype, wavelet,
+                                    scheme, tile);
+    if (st) return st;
+    return fwd_level(in, in_pitch, in_dtype, width, height, ll, ll_pitch, ll_dtype, hl, lh, hh,
+                     band_pitch, band_dtype, wavelet, scheme, tile, (hipStream_t)stream);
+}
+
+int dwt2_inverse_level(const void *ll, int64_t ll_pitch, int32_t ll_dtype, const void *hl,
+                       const void *lh, const void *hh, int64_t band_pitch, int32_t band_dtype,
+                       void *out, int64_t out_pitch, int32_t out_dtype, int32_t width,
+                       int32_t height, int32_t wavelet, int32_t scheme, int32_t tile,
+                       void *stream) {
+    const int st = check_level_args(out, out_pitch, out_dtype, width, height, ll, ll_pitch,
+                                    ll_dtype, hl, lh, hh, band_pitch, band_dtype, wavelet,
+                                    scheme, tile);
+    if (st) return st;
+    return inv_level(ll, ll_pitch, ll_dtype, hl, lh, hh, band_pitch, band_dtype, out, out_pitch,
+                     out_dtype, width, height, wavelet, scheme, tile, (hipStream_t)stream);
+}
+
+int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
+                 int32_t wavelet, int32_t levels, int32_t boundary, int32_t scheme,
+                 const int32_t *tiles, void *workspace, size_t workspace_bytes,
+                 void *const *level_events, void *stream) {
+    int st = check_multi(src, src_d, coef, coef_d, wavelet, levels, boundary, scheme, tiles,
+                         workspace, workspace_bytes);
+    if (st) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    const int32_t W = src_d->width, H = src_d->height, T = src_d->dtype;
+    const size_t es = elem_size(T);
+    float *ws[2] = {static_cast<float *>(workspace),
+                    workspace ? static_cast<float *>(workspace) + (size_t)(W / 2) * (H / 2)
+                              : nullptr};
+    char *cbase = static_cast<char *>(coef);
+    const int64_t cp = coef_d->pitch;
+    for (int j = 1; j <= levels; ++j) {
+        const int w = W >> (j - 1), h = H >> (j - 1);
+        const void *in = j == 1 ? src : (const void *)ws[(j - 2) & 1];
+        const int64_t in_pitch = j == 1 ? src_d->pitch : w;
+        const int in_dt = j == 1 ? T : DWT2_F32;
+        void *hl = cbase + (size_t)(w / 2) * es;
+        void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
+        void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
+        void *ll = j == levels ? (void *)coef : (void *)ws[(j - 1) & 1];
+        const int64_t ll_pitch = j == levels ? cp : w / 2;
+        const int ll_dt = j == levels ? T : DWT2_F32;
+        const int tile = tiles ? tiles[j - 1] : -1;
+        if ((st = record(level_events, 2 * (j - 1), s))) return st;
+        st = fwd_level(in, in_pitch, in_dt, w, h, ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, wavelet,
+                       scheme, tile, s);
+        if (st) return st;
+        if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
+    }
+    return DWT2_OK;
+}
+
+int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt2_desc *dst_d,
+                 int32_t wavelet, int32_t levels, int32_t boundary, int32_t scheme,
+                 const int32_t *tiles, void *workspace, size_t workspace_bytes,
+                 void *const *level_events, void *stream) {
+    int st = check_multi(coef, coef_d, dst, dst_d, wavelet, levels, boundary, scheme, tiles,
+                         workspace, workspace_bytes);
+    if (st) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    const int32_t W = coef_d->width, H = coef_d->height, T = coef_d->dtype;
+    const size_t es = elem_size(T);
+    float *ws[2] = {static_cast<float *>(workspace),
+                    workspace ? static_cast<float *>(workspace) + (size_t)(W / 2) * (H / 2)
+                              : nullptr};
+    const char *cbase = static_cast<const char *>(coef);
+    const int64_t cp = coef_d->pitch;
+    for (int j = levels; j >= 1; --j) {
+        const int w = W >> (j - 1), h = H >> (j - 1);
+        const void *ll = j == levels ? coef : (const void *)ws[(j - 1) & 1];
+        const int64_t ll_pitch = j == levels ? cp : w / 2;
+        const int ll_dt = j == levels ? T : DWT2_F32;
+        const void *hl = cbase + (size_t)(w / 2) * es;
+        const void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
+        const void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
+        void *out = j == 1 ? dst : (void *)ws[(j - 2) & 1];
+        const int64_t out_pitch = j == 1 ? dst_d->pitch : w;
+        const int out_dt = j == 1 ? T : DWT2_F32;
+        const int tile = tiles ? tiles[j - 1] : -1;
+        if ((st = record(level_events, 2 * (j - 1), s))) return st;
+        st = inv_level(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out, out_pitch, out_dt, w, h,
+                       wavelet, scheme, tile, s);
+        if (st) return st;
+        if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
+    }
+    return DWT2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,449 @@
+// Device-side building blocks of the 2-D lifting DWT for gfx950 (CDNA4).
+//
+// Data layout in registers. A workgroup owns a window of quads: 64 lanes per
+// wavefront along x, each lane holding QPL consecutive quads of a quad row,
+// and ROWS quad rows per lane; WAVES wavefronts are stacked along y. A quad is
+// the 2x2 polyphase block (a, b, c, d) = (x[2j][2i], x[2j][2i+1],
+// x[2j+1][2i], x[2j+1][2i+1]), the paper's components 1..4 (Sec. 2).
+//
+// Neighbour exchange. Horizontal neighbours of the first/last quad of a lane
+// come from the adjacent lane through DPP wavefront shifts (no LDS, no
+// barrier); vertical neighbours inside a lane's rows are registers; the rows
+// on the boundary between two wavefronts go through a small double-buffered
+// LDS mailbox, one workgroup barrier per exchange. Window edges read
+// don't-care values; the lifting halo around the written centre absorbs them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace dwt2 {
+
+enum : int { CDF97 = 0, CDF53 = 1 };
+enum : int { NONSEP = 0, SEP = 1 };
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+// ---- lifting constants ------------------------------------------------------
+// CDF 9/7: two pairs (alpha, beta), (gamma, delta) and the scaling K; CDF 5/3:
+// one pair (-1/2, 1/4). Predicts P(z) = p (1 + z), updates U(z) = u (1 + 1/z).
+// Unit-gain scaling: low phase * 1/K, high phase * K/2 (5/3: 1 and 1/2).
+template <int WV> struct Wavelet;
+
+template <> struct Wavelet<CDF97> {
+    static constexpr int NPAIRS = 2;
+    static constexpr double K = 1.230174104914001;
+    __device__ static constexpr double p(int k) { return k == 0 ? -1.586134342059924 : 0.882911075530934; }
+    __device__ static constexpr double u(int k) { return k == 0 ? -0.052980118572961 : 0.443506852043971; }
+    static constexpr double ZL = 1.0 / K;
+    static constexpr double ZH = K / 2.0;
+};
+
+template <> struct Wavelet<CDF53> {
+    static constexpr int NPAIRS = 1;
+    __device__ static constexpr double p(int) { return -0.5; }
+    __device__ static constexpr double u(int) { return 0.25; }
+    static constexpr double ZL = 1.0;
+    static constexpr double ZH = 0.5;
+};
+
+// ---- storage types ----------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+
+template <typename T> struct Storage;
+template <> struct Storage<float> {
+    static constexpr int code = DT_F32;
+    __device__ static float decode(uint32_t v) { return __uint_as_float(v); }
+};
+template <> struct Storage<__half> {
+    static constexpr int code = DT_F16;
+    __device__ static float decode(uint32_t v) {
+        return __half2float(__ushort_as_half((unsigned short)v));
+    }
+};
+template <> struct Storage<bf16_t> {
+    static constexpr int code = DT_BF16;
+    __device__ static float decode(uint32_t v) { return __uint_as_float(v << 16); }
+};
+
+__device__ __forceinline__ float to_float(float v) { return v; }
+__device__ __forceinline__ float to_float(__half v) { return __half2float(v); }
+__device__ __forceinline__ float to_float(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+
+// Round-to-nearest-even conversions from FP32.
+template <typename T> __device__ __forceinline__ T from_float(float v);
+template <> __device__ __forceinline__ float from_float<float>(float v) { return v; }
+template <> __device__ __forceinline__ __half from_float<__half>(float v) { return __float2half_rn(v); }
+template <> __device__ __forceinline__ bf16_t from_float<bf16_t>(float v) {
+    uint32_t u = __float_as_uint(v);
+    bf16_t r;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        r.bits = 0x7fc0;                       // quiet NaN
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);       // round half to even
+        r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ uint32_t bits_of(T v);
+template <> __device__ __forceinline__ uint32_t bits_of<float>(float v) { return __float_as_uint(v); }
+template <> __device__ __forceinline__ uint32_t bits_of<__half>(__half v) { return (uint32_t)__half_as_ushort(v); }
+template <> __device__ __forceinline__ uint32_t bits_of<bf16_t>(bf16_t v) { return v.bits; }
+
+// N consecutive elements as one vector memory access (N*sizeof(T) in 8..32 B,
+// pointer aligned to min(16, N*sizeof(T))).
+template <typename T, int N>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, float (&out)[N]) {
+    constexpr int BYTES = N * (int)sizeof(T);
+    static_assert(BYTES == 4 || BYTES == 8 || BYTES == 16 || BYTES == 32, "vector width");
+    if constexpr (sizeof(T) == 4) {
+        static_assert(BYTES >= 8, "at least two FP32 elements");
+        if constexpr (BYTES == 8) {
+            float2 v = *reinterpret_cast<const float2 *>(p);
+            out[0] = v.x; out[1] = v.y;
+        } else {
+#pragma unroll
+            for (int h = 0; h < BYTES / 16; ++h) {
+                float4 v = *reinterpret_cast<const float4 *>(p + 4 * h);
+                out[4 * h + 0] = v.x; out[4 * h + 1] = v.y;
+                out[4 * h + 2] = v.z; out[4 * h + 3] = v.w;
+            }
+        }
+    } else {
+        uint32_t w[BYTES / 4];
+        if constexpr (BYTES == 4) {
+            w[0] = *reinterpret_cast<const uint32_t *>(p);
+        } else if constexpr (BYTES == 8) {
+            uint2 v = *reinterpret_cast<const uint2 *>(p);
+            w[0] = v.x; w[1] = v.y;
+        } else {
+#pragma unroll
+            for (int h = 0; h < BYTES / 16; ++h) {
+                uint4 v = *reinterpret_cast<const uint4 *>(p + 8 * h);
+                w[4 * h + 0] = v.x; w[4 * h + 1] = v.y;
+                w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = Storage<T>::decode((w[e / 2] >> (16 * (e & 1))) & 0xffffu);
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const float (&in)[N]) {
+    constexpr int BYTES = N * (int)sizeof(T);
+    static_assert(BYTES == 4 || BYTES == 8 || BYTES == 16 || BYTES == 32, "vector width");
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (BYTES == 8) {
+            *reinterpret_cast<float2 *>(p) = make_float2(in[0], in[1]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < BYTES / 16; ++h)
+                *reinterpret_cast<float4 *>(p + 4 * h) =
+                    make_float4(in[4 * h], in[4 * h + 1], in[4 * h + 2], in[4 * h + 3]);
+        }
+    } else {
+        uint32_t w[(BYTES + 3) / 4];
+#pragma unroll
+        for (int e = 0; e < N; e += 2)
+            w[e / 2] = bits_of<T>(from_float<T>(in[e])) |
+                       (bits_of<T>(from_float<T>(in[e + 1])) << 16);
+        if constexpr (BYTES == 4) {
+            *reinterpret_cast<uint32_t *>(p) = w[0];
+        } else if constexpr (BYTES == 8) {
+            *reinterpret_cast<uint2 *>(p) = make_uint2(w[0], w[1]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < BYTES / 16; ++h)
+                *reinterpret_cast<uint4 *>(p + 8 * h) =
+                    make_uint4(w[4 * h], w[4 * h + 1], w[4 * h + 2], w[4 * h + 3]);
+        }
+    }
+}
+
+// ---- boundary ---------------------------------------------------------------
+// Whole-sample symmetric extension of an n-sample axis (n >= 2), periodic
+// with period 2n-2: the index of the sample that position x stands for.
+__device__ __forceinline__ int mirror(int x, int n) {
+    const int period = 2 * n - 2;
+    x %= period;
+    if (x < 0) x += period;
+    return x < n ? x : period - x;
+}
+
+// ---- cross-lane shifts (DPP, wavefront-wide) ----------------------------------
+// from_right(v): lane l receives lane l+1's v (lane 63 receives 0).
+// from_left(v):  lane l receives lane l-1's v (lane 0 receives 0).
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// ---- the register tile --------------------------------------------------------
+template <int ROWS, int QPL>
+struct Quads {
+    float a[ROWS][QPL], b[ROWS][QPL], c[ROWS][QPL], d[ROWS][QPL];
+};
+
+// Mailbox between vertically adjacent wavefronts. Two buffers alternate so
+// that one barrier per exchange suffices: the writes of exchange k+1 go to the
+// buffer last read in exchange k-1, which every wave finished before it
+// passed the barrier of exchange k.
+template <int QPL, int WAVES>
+struct Mailbox {
+    float v[2][WAVES][2][QPL][64];
+};
+
+template <int ROWS, int QPL, int WAVES>
+struct Exchange {
+    Mailbox<QPL, WAVES> *box;
+    int wave, lane, buf;
+
+    // Every wave sends its first row's (x, y) up and receives the first row of
+    // the wave below it (the row after its last row).
+    __device__ __forceinline__ void from_below(const float (&x0)[QPL], const float (&y0)[QPL],
+                                               float (&xo)[QPL], float (&yo)[QPL]) {
+        if constexpr (WAVES == 1) {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) { xo[i] = x0[i]; yo[i] = y0[i]; }
+        } else {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                box->v[buf][wave][0][i][lane] = x0[i];
+                box->v[buf][wave][1][i][lane] = y0[i];
+            }
+            __syncthreads();
+            const int src = (wave + 1 < WAVES) ? wave + 1 : wave;
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                xo[i] = box->v[buf][src][0][i][lane];
+                yo[i] = box->v[buf][src][1][i][lane];
+            }
+            buf ^= 1;
+        }
+    }
+
+    // Every wave sends its last row's (x, y) down and receives the last row of
+    // the wave above it (the row before its first row).
+    __device__ __forceinline__ void from_above(const float (&xl)[QPL], const float (&yl)[QPL],
+                                               float (&xo)[QPL], float (&yo)[QPL]) {
+        if constexpr (WAVES == 1) {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) { xo[i] = xl[i]; yo[i] = yl[i]; }
+        } else {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                box->v[buf][wave][0][i][lane] = xl[i];
+                box->v[buf][wave][1][i][lane] = yl[i];
+            }
+            __syncthreads();
+            const int src = (wave > 0) ? wave - 1 : wave;
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                xo[i] = box->v[buf][src][0][i][lane];
+                yo[i] = box->v[buf][src][1][i][lane];
+            }
+            buf ^= 1;
+        }
+    }
+};
+
+// ---- non-separable steps (Sec. 3) ---------------------------------------------
+// T_P:  b += P a;  c += P* a;  d += P P* a + P* b + P c   (pre-step values)
+// computed as the spatial T_{P1} with P1 = p z (right and lower neighbours),
+// followed on the unit's own quad by T^H_{P0} then T^V_{P0} with P0 = p.
+// Rows run top to bottom and quads left to right, so every neighbour read
+// (row below, quad to the right) still holds its pre-step value.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void nonsep_predict(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x,
+                                               float p) {
+    const float pp = p * p;
+    float na[QPL], nb[QPL];
+    x.from_below(q.a[0], q.b[0], na, nb);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        constexpr int dummy = 0; (void)dummy;
+        float ad[QPL], bd[QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            ad[i] = (r + 1 < ROWS) ? q.a[(r + 1 < ROWS) ? r + 1 : r][i] : na[i];
+            bd[i] = (r + 1 < ROWS) ? q.b[(r + 1 < ROWS) ? r + 1 : r][i] : nb[i];
+        }
+        const float aR = from_right(q.a[r][0]);
+        const float cR = from_right(q.c[r][0]);
+        const float adR = from_right(ad[0]);
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float ar = (i + 1 < QPL) ? q.a[r][(i + 1 < QPL) ? i + 1 : i] : aR;
+            const float cr = (i + 1 < QPL) ? q.c[r][(i + 1 < QPL) ? i + 1 : i] : cR;
+            const float adr = (i + 1 < QPL) ? ad[(i + 1 < QPL) ? i + 1 : i] : adR;
+            const float a = q.a[r][i];
+            float b = fmaf(p, ar, q.b[r][i]);
+            float c = fmaf(p, ad[i], q.c[r][i]);
+            float d = fmaf(p, cr, q.d[r][i]);
+            d = fmaf(p, bd[i], d);
+            d = fmaf(pp, adr, d);
+            b = fmaf(p, a, b);      // T^H_{P0}
+            d = fmaf(p, c, d);
+            c = fmaf(p, a, c);      // T^V_{P0}
+            d = fmaf(p, b, d);
+            q.b[r][i] = b; q.c[r][i] = c; q.d[r][i] = d;
+        }
+    }
+}
+
+// S_U:  a += U b + U* c + U U* d;  b += U* d;  c += U d   (pre-step values)
+// computed as the spatial S_{U1} with U1 = u / z (left and upper neighbours),
+// followed by S^H_{U0} then S^V_{U0} with U0 = u. Rows run bottom to top and
+// quads right to left so neighbour reads see pre-step values.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void nonsep_update(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x,
+                                              float u) {
+    const float uu = u * u;
+    float pc[QPL], pd[QPL];
+    x.from_above(q.c[ROWS - 1], q.d[ROWS - 1], pc, pd);
+#pragma unroll
+    for (int r = ROWS - 1; r >= 0; --r) {
+        float cu[QPL], du[QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            cu[i] = (r > 0) ? q.c[(r > 0) ? r - 1 : r][i] : pc[i];
+            du[i] = (r > 0) ? q.d[(r > 0) ? r - 1 : r][i] : pd[i];
+        }
+        const float bL = from_left(q.b[r][QPL - 1]);
+        const float dL = from_left(q.d[r][QPL - 1]);
+        const float duL = from_left(du[QPL - 1]);
+#pragma unroll
+        for (int i = QPL - 1; i >= 0; --i) {
+            const float bl = (i > 0) ? q.b[r][(i > 0) ? i - 1 : i] : bL;
+            const float dl = (i > 0) ? q.d[r][(i > 0) ? i - 1 : i] : dL;
+            const float dul = (i > 0) ? du[(i > 0) ? i - 1 : i] : duL;
+            const float d = q.d[r][i];
+            float a = fmaf(u, bl, q.a[r][i]);
+            a = fmaf(u, cu[i], a);
+            a = fmaf(uu, dul, a);
+            float b = fmaf(u, du[i], q.b[r][i]);
+            float c = fmaf(u, dl, q.c[r][i]);
+            a = fmaf(u, b, a);      // S^H_{U0}
+            c = fmaf(u, d, c);
+            a = fmaf(u, c, a);      // S^V_{U0}
+            b = fmaf(u, d, b);
+            q.a[r][i] = a; q.b[r][i] = b; q.c[r][i] = c;
+        }
+    }
+}
+
+// ---- separable steps (Sec. 2) -------------------------------------------------
+// T^H_P: b += P a, d += P c.  Horizontal only: DPP exchange, no barrier.
+template <int ROWS, int QPL>
+__device__ __forceinline__ void sep_predict_h(Quads<ROWS, QPL> &q, float p) {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const float aR = from_right(q.a[r][0]);
+        const float cR = from_right(q.c[r][0]);
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float ar = (i + 1 < QPL) ? q.a[r][(i + 1 < QPL) ? i + 1 : i] : aR;
+            const float cr = (i + 1 < QPL) ? q.c[r][(i + 1 < QPL) ? i + 1 : i] : cR;
+            q.b[r][i] = fmaf(p, ar, fmaf(p, q.a[r][i], q.b[r][i]));
+            q.d[r][i] = fmaf(p, cr, fmaf(p, q.c[r][i], q.d[r][i]));
+        }
+    }
+}
+
+// T^V_P: c += P* a, d += P* b.  Vertical: one mailbox exchange.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void sep_predict_v(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x,
+                                              float p) {
+    float na[QPL], nb[QPL];
+    x.from_below(q.a[0], q.b[0], na, nb);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float ad = (r + 1 < ROWS) ? q.a[(r + 1 < ROWS) ? r + 1 : r][i] : na[i];
+            const float bd = (r + 1 < ROWS) ? q.b[(r + 1 < ROWS) ? r + 1 : r][i] : nb[i];
+            q.c[r][i] = fmaf(p, ad, fmaf(p, q.a[r][i], q.c[r][i]));
+            q.d[r][i] = fmaf(p, bd, fmaf(p, q.b[r][i], q.d[r][i]));
+        }
+    }
+}
+
+// S^H_U: a += U b, c += U d.
+template <int ROWS, int QPL>
+__device__ __forceinline__ void sep_update_h(Quads<ROWS, QPL> &q, float u) {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const float bL = from_left(q.b[r][QPL - 1]);
+        const float dL = from_left(q.d[r][QPL - 1]);
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float bl = (i > 0) ? q.b[r][(i > 0) ? i - 1 : i] : bL;
+            const float dl = (i > 0) ? q.d[r][(i > 0) ? i - 1 : i] : dL;
+            q.a[r][i] = fmaf(u, bl, fmaf(u, q.b[r][i], q.a[r][i]));
+            q.c[r][i] = fmaf(u, dl, fmaf(u, q.d[r][i], q.c[r][i]));
+        }
+    }
+}
+
+// S^V_U: a += U* c, b += U* d.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void sep_update_v(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x,
+                                             float u) {
+    float pc[QPL], pd[QPL];
+    x.from_above(q.c[ROWS - 1], q.d[ROWS - 1], pc, pd);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float cu = (r > 0) ? q.c[(r > 0) ? r - 1 : r][i] : pc[i];
+            const float du = (r > 0) ? q.d[(r > 0) ? r - 1 : r][i] : pd[i];
+            q.a[r][i] = fmaf(u, cu, fmaf(u, q.c[r][i], q.a[r][i]));
+            q.b[r][i] = fmaf(u, du, fmaf(u, q.d[r][i], q.b[r][i]));
+        }
+    }
+}
+
+// ---- whole lifting sequences --------------------------------------------------
+template <int WV, int SCH, int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void lift_forward(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x) {
+    using L = Wavelet<WV>;
+#pragma unroll
+    for (int k = 0; k < L::NPAIRS; ++k) {
+        const float p = (float)L::p(k), u = (float)L::u(k);
+        if constexpr (SCH == NONSEP) {
+            nonsep_predict(q, x, p);
+            nonsep_update(q, x, u);
+        } else {
+            sep_predict_h(q, p);
+            sep_predict_v(q, x, p);
+            sep_update_h(q, u);
+            sep_update_v(q, x, u);
+        }
+    }
+}
+
+// The inverse undoes each step with the negated filter, in reverse order.
+template <int WV, int SCH, int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void lift_inverse(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x) {
+    using L = Wavelet<WV>;
+#pragma unroll
+    for (int k = L::NPAIRS - 1; k >= 0; --k) {
+        const float p = -(float)L::p(k), u = -(float)L::u(k);
+        if constexpr (SCH == NONSEP) {
+            nonsep_update(q, x, u);
+            nonsep_predict(q, x, p);
+        } else {
+            sep_update_v(q, x, u);
+            sep_update_h(q, u);
+            sep_predict_v(q, x, p);
+            sep_predict_h(q, p);
+        }
+    }
+}
+
+}  // namespace dwt2

@@ -1,0 +1,252 @@
+// One-level forward and inverse 2-D DWT kernels for gfx950.
+//
+// One launch computes one level: each workgroup reads its window of the level
+// input once from HBM (coalesced vector loads straight into registers, the
+// lifting halo included), runs every lifting step of the level in registers
+// (non-separable: S_U | T_P per lifting pair, Sec. 3; separable:
+// S_U^V | S_U^H | T_P^V | T_P^H, Sec. 2), scales, and writes the centre of
+// the window: the four bands (forward) or the interleaved pixels (inverse).
+#pragma once
+
+#include "dwt2_device.hpp"
+
+namespace dwt2 {
+
+// Parameters of one forward level. The input is w x h pixels (even), the
+// outputs are nqx x nqy = (w/2) x (h/2) quads per band.
+struct FwdParams {
+    const void *in;
+    int64_t in_pitch;
+    void *ll;
+    int64_t ll_pitch;
+    void *hl, *lh, *hh;
+    int64_t band_pitch;
+    int32_t w, h, nqx, nqy;
+    int32_t tiles_x, tiles_y;
+    int32_t vec_in, vec_ll, vec_band;   // 1 when vector accesses are aligned
+};
+
+struct InvParams {
+    const void *ll;
+    int64_t ll_pitch;
+    const void *hl, *lh, *hh;
+    int64_t band_pitch;
+    void *out;
+    int64_t out_pitch;
+    int32_t w, h, nqx, nqy;
+    int32_t tiles_x, tiles_y;
+    int32_t vec_ll, vec_band, vec_out;
+};
+
+// Geometry of a tile configuration. The horizontal halo is one lane's worth
+// of quads on each side (>= the number of lifting pairs), which keeps every
+// lane's loads and stores aligned to its vector width; the vertical halo is
+// one quad row per lifting pair.
+template <int WV, int QPL, int ROWS, int WAVES>
+struct TileGeom {
+    static constexpr int NP = Wavelet<WV>::NPAIRS;
+    static constexpr int HX = QPL;
+    static constexpr int HY = NP;
+    static constexpr int OX = 64 * QPL - 2 * HX;
+    static constexpr int OY = WAVES * ROWS - 2 * HY;
+    static_assert(HX >= NP, "horizontal halo must cover the lifting support");
+    static_assert(OY > 0, "tile too short for the lifting halo");
+};
+
+// The hardware hands consecutive workgroup ids to the 8 XCDs in turn. Remap
+// so that each XCD gets one contiguous run of tiles (row-major), keeping the
+// halo rows shared by vertically adjacent tiles in the same L2.
+__device__ __forceinline__ int xcd_contiguous_tile(int b, int n) {
+    const int per = n >> 3, rem = n & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
+    using G = TileGeom<WV, QPL, ROWS, WAVES>;
+    __shared__ Mailbox<QPL, (WAVES > 1 ? WAVES : 1)> box;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+    const int ty = tile / prm.tiles_x;
+    const int tx = tile - ty * prm.tiles_x;
+    const int qx0 = tx * G::OX - G::HX + lane * QPL;   // first quad column of the lane
+    const int qy0 = ty * G::OY - G::HY + wave * ROWS;  // first quad row of the lane
+
+    // ---- load: two pixel rows per quad row, 2*QPL pixels per row per lane
+    Quads<ROWS, QPL> q;
+    const TIN *in = static_cast<const TIN *>(prm.in);
+    const int px0 = 2 * qx0;
+    const bool lane_inside = prm.vec_in && px0 >= 0 && px0 + 2 * QPL <= prm.w;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int py = 2 * (qy0 + r);
+        if (lane_inside && py >= 0 && py + 2 <= prm.h) {
+            float e[2 * QPL], o[2 * QPL];
+            load_vec<TIN, 2 * QPL>(in + (int64_t)py * prm.in_pitch + px0, e);
+            load_vec<TIN, 2 * QPL>(in + (int64_t)(py + 1) * prm.in_pitch + px0, o);
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                q.a[r][i] = e[2 * i]; q.b[r][i] = e[2 * i + 1];
+                q.c[r][i] = o[2 * i]; q.d[r][i] = o[2 * i + 1];
+            }
+        } else {
+            const TIN *r0 = in + (int64_t)mirror(py, prm.h) * prm.in_pitch;
+            const TIN *r1 = in + (int64_t)mirror(py + 1, prm.h) * prm.in_pitch;
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                const int xe = mirror(px0 + 2 * i, prm.w);
+                const int xo = mirror(px0 + 2 * i + 1, prm.w);
+                q.a[r][i] = to_float(r0[xe]); q.b[r][i] = to_float(r0[xo]);
+                q.c[r][i] = to_float(r1[xe]); q.d[r][i] = to_float(r1[xo]);
+            }
+        }
+    }
+
+    // ---- all lifting steps of the level, in registers
+    Exchange<ROWS, QPL, WAVES> x{reinterpret_cast<Mailbox<QPL, WAVES> *>(&box), wave, lane, 0};
+    lift_forward<WV, SCH>(q, x);
+
+    // ---- scale and store the centre of the window
+    using L = Wavelet<WV>;
+    const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
+    const float sHH = (float)(L::ZH * L::ZH);
+    if (lane == 0 || lane == 63) return;
+    TLL *ll = static_cast<TLL *>(prm.ll);
+    TB *hl = static_cast<TB *>(prm.hl);
+    TB *lh = static_cast<TB *>(prm.lh);
+    TB *hh = static_cast<TB *>(prm.hh);
+    const bool full_x = qx0 + QPL <= prm.nqx;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int wr = wave * ROWS + r;
+        const int gy = qy0 + r;
+        if (wr < G::HY || wr >= WAVES * ROWS - G::HY || gy >= prm.nqy) continue;
+        float va[QPL], vb[QPL], vc[QPL], vd[QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            va[i] = q.a[r][i] * sLL; vb[i] = q.b[r][i] * sHL;
+            vc[i] = q.c[r][i] * sHL; vd[i] = q.d[r][i] * sHH;
+        }
+        const int64_t ob = (int64_t)gy * prm.band_pitch + qx0;
+        const int64_t ol = (int64_t)gy * prm.ll_pitch + qx0;
+        if (full_x && prm.vec_ll) {
+            store_vec<TLL, QPL>(ll + ol, va);
+        } else {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i)
+                if (qx0 + i < prm.nqx) ll[ol + i] = from_float<TLL>(va[i]);
+        }
+        if (full_x && prm.vec_band) {
+            store_vec<TB, QPL>(hl + ob, vb);
+            store_vec<TB, QPL>(lh + ob, vc);
+            store_vec<TB, QPL>(hh + ob, vd);
+        } else {
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                if (qx0 + i < prm.nqx) {
+                    hl[ob + i] = from_float<TB>(vb[i]);
+                    lh[ob + i] = from_float<TB>(vc[i]);
+                    hh[ob + i] = from_float<TB>(vd[i]);
+                }
+            }
+        }
+    }
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
+    using G = TileGeom<WV, QPL, ROWS, WAVES>;
+    __shared__ Mailbox<QPL, (WAVES > 1 ? WAVES : 1)> box;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = xcd_contiguous_tile(blockIdx.x, gridDim.x);
+    const int ty = tile / prm.tiles_x;
+    const int tx = tile - ty * prm.tiles_x;
+    const int qx0 = tx * G::OX - G::HX + lane * QPL;
+    const int qy0 = ty * G::OY - G::HY + wave * ROWS;
+
+    // ---- load the four bands. Outside the level, each polyphase component is
+    // extended through the symmetric extension of the pixel grid it lives on:
+    // quad (i, j) component b stands for pixel (2i+1, 2j), and so on.
+    Quads<ROWS, QPL> q;
+    const TLL *ll = static_cast<const TLL *>(prm.ll);
+    const TB *hl = static_cast<const TB *>(prm.hl);
+    const TB *lh = static_cast<const TB *>(prm.lh);
+    const TB *hh = static_cast<const TB *>(prm.hh);
+    const bool lane_inside = prm.vec_ll && prm.vec_band && qx0 >= 0 && qx0 + QPL <= prm.nqx;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int gy = qy0 + r;
+        if (lane_inside && gy >= 0 && gy < prm.nqy) {
+            const int64_t ob = (int64_t)gy * prm.band_pitch + qx0;
+            load_vec<TLL, QPL>(ll + (int64_t)gy * prm.ll_pitch + qx0, q.a[r]);
+            load_vec<TB, QPL>(hl + ob, q.b[r]);
+            load_vec<TB, QPL>(lh + ob, q.c[r]);
+            load_vec<TB, QPL>(hh + ob, q.d[r]);
+        } else {
+            const int ye = mirror(2 * gy, prm.h) >> 1;
+            const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
+#pragma unroll
+            for (int i = 0; i < QPL; ++i) {
+                const int xe = mirror(2 * (qx0 + i), prm.w) >> 1;
+                const int xo = (mirror(2 * (qx0 + i) + 1, prm.w) - 1) >> 1;
+                q.a[r][i] = to_float(ll[(int64_t)ye * prm.ll_pitch + xe]);
+                q.b[r][i] = to_float(hl[(int64_t)ye * prm.band_pitch + xo]);
+                q.c[r][i] = to_float(lh[(int64_t)yo * prm.band_pitch + xe]);
+                q.d[r][i] = to_float(hh[(int64_t)yo * prm.band_pitch + xo]);
+            }
+        }
+    }
+
+    // ---- undo the scaling, then the lifting steps in reverse
+    using L = Wavelet<WV>;
+    const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
+    const float uHH = (float)(1.0 / (L::ZH * L::ZH));
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            q.a[r][i] *= uLL; q.b[r][i] *= uHL; q.c[r][i] *= uHL; q.d[r][i] *= uHH;
+        }
+    }
+    Exchange<ROWS, QPL, WAVES> x{reinterpret_cast<Mailbox<QPL, WAVES> *>(&box), wave, lane, 0};
+    lift_inverse<WV, SCH>(q, x);
+
+    // ---- store interleaved pixels of the window centre
+    if (lane == 0 || lane == 63) return;
+    TOUT *out = static_cast<TOUT *>(prm.out);
+    const int px0 = 2 * qx0;
+    const bool full_x = prm.vec_out && px0 + 2 * QPL <= prm.w;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int wr = wave * ROWS + r;
+        const int gy = qy0 + r;
+        if (wr < G::HY || wr >= WAVES * ROWS - G::HY || gy >= prm.nqy) continue;
+        float e[2 * QPL], o[2 * QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            e[2 * i] = q.a[r][i]; e[2 * i + 1] = q.b[r][i];
+            o[2 * i] = q.c[r][i]; o[2 * i + 1] = q.d[r][i];
+        }
+        TOUT *r0 = out + (int64_t)(2 * gy) * prm.out_pitch;
+        TOUT *r1 = r0 + prm.out_pitch;
+        if (full_x) {
+            store_vec<TOUT, 2 * QPL>(r0 + px0, e);
+            store_vec<TOUT, 2 * QPL>(r1 + px0, o);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2 * QPL; ++k) {
+                if (px0 + k < prm.w) {
+                    r0[px0 + k] = from_float<TOUT>(e[k]);
+                    r1[px0 + k] = from_float<TOUT>(o[k]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace dwt2

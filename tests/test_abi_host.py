@@ -1,0 +1,139 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before enqueuing anything (no GPU needed:
+every call here returns during argument checking)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1705_08266_amd as dwt
+from paper_1705_08266_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwt2.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(dwt2_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_is_built_and_loads():
+    assert os.path.exists(_lib.LIB_PATH)
+    lib = _lib.load()
+    assert lib.dwt2_version() >= 100
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared_functions()
+    assert len(names) == len(_lib.SIGNATURES)
+    lib = _lib.load()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, f"{n} missing from the Python binding"
+
+
+def test_workspace_bytes():
+    lib = _lib.load()
+    assert lib.dwt2_workspace_bytes(64, 64, 1) == 0
+    assert lib.dwt2_workspace_bytes(64, 64, 2) == 32 * 32 * 4
+    assert lib.dwt2_workspace_bytes(64, 64, 3) == (32 * 32 + 16 * 16) * 4
+    assert lib.dwt2_workspace_bytes(4096, 4096, 5) == (2048 * 2048 + 1024 * 1024) * 4
+    assert lib.dwt2_workspace_bytes(48, 64, 5) == 0          # 48 not divisible by 32
+    assert lib.dwt2_workspace_bytes(64, 64, 0) == 0
+
+
+def test_tile_configs_cover_the_lifting_halo():
+    for w, np_ in (("cdf97", 2), ("cdf53", 1)):
+        cfgs = dwt.tile_configs(w)
+        assert len(cfgs) >= 4
+        for (t, qpl, rows, waves, ox, oy) in cfgs:
+            assert qpl >= np_                        # one halo lane each side
+            assert ox == 64 * qpl - 2 * qpl
+            assert oy == waves * rows - 2 * np_ > 0
+
+
+def test_default_tile_is_valid():
+    n = _lib.load().dwt2_tile_config_count()
+    for (w, h) in ((4096, 4096), (256, 256), (2, 2), (16384, 64)):
+        t = dwt.default_tile(w, h)
+        assert 0 <= t < n
+    assert dwt.default_tile(3, 4) == _lib.ERR_INVALID_ARG
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for s in (0, -1, -2, -3, -4, 17):
+        assert lib.dwt2_status_string(s)
+
+
+FAKE = 0x10000000       # never dereferenced: every call below fails its checks
+
+
+def _fwd(src=FAKE, sd=None, dst=FAKE + (1 << 30), dd=None, wavelet=0, levels=1,
+         boundary=0, scheme=0, tiles=None, ws=None, wsb=0):
+    lib = _lib.load()
+    sd = sd or _lib.Desc(64, 64, 64, _lib.F32)
+    dd = dd or _lib.Desc(64, 64, 64, _lib.F32)
+    return lib.dwt2_forward(src, ctypes.byref(sd), dst, ctypes.byref(dd), wavelet, levels,
+                            boundary, scheme, tiles, ws, wsb, None, None)
+
+
+def test_forward_argument_errors():
+    E, U, W = _lib.ERR_INVALID_ARG, _lib.ERR_UNSUPPORTED, _lib.ERR_WORKSPACE
+    assert _fwd(src=None) == E
+    assert _fwd(dst=None) == E
+    assert _fwd(levels=0) == E
+    assert _fwd(levels=17) == E
+    assert _fwd(levels=7) == E                                   # 64 % 128 != 0
+    assert _fwd(wavelet=5) == U
+    assert _fwd(scheme=9) == U
+    assert _fwd(boundary=1) == U
+    assert _fwd(sd=_lib.Desc(64, 64, 32, _lib.F32)) == E         # pitch < width
+    assert _fwd(dd=_lib.Desc(64, 32, 64, _lib.F32)) == E         # shape mismatch
+    assert _fwd(dd=_lib.Desc(64, 64, 64, _lib.F16)) == E         # dtype mismatch
+    assert _fwd(sd=_lib.Desc(64, 64, 64, 7), dd=_lib.Desc(64, 64, 64, 7)) == U
+    assert _fwd(dst=FAKE + 64) == E                              # overlap
+    assert _fwd(levels=2) == W                                   # no workspace
+    assert _fwd(levels=2, ws=FAKE + (2 << 30), wsb=100) == W     # too small
+    assert _fwd(levels=2, ws=FAKE + 4, wsb=1 << 20) == E         # workspace overlaps
+    bad = (ctypes.c_int32 * 1)(99)
+    assert _fwd(tiles=bad) == U
+    assert _fwd(sd=_lib.Desc(66, 64, 66, _lib.F32), dd=_lib.Desc(66, 64, 66, _lib.F32),
+                levels=2) == E                                   # 66 % 4 != 0
+
+
+def test_inverse_argument_errors():
+    lib = _lib.load()
+    d = _lib.Desc(32, 32, 32, _lib.F32)
+    assert lib.dwt2_inverse(None, ctypes.byref(d), FAKE, ctypes.byref(d), 0, 1, 0, 0,
+                            None, None, 0, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.dwt2_inverse(FAKE, ctypes.byref(d), FAKE + 8, ctypes.byref(d), 0, 1, 0, 0,
+                            None, None, 0, None, None) == _lib.ERR_INVALID_ARG
+
+
+def test_level_argument_errors():
+    lib = _lib.load()
+    B = FAKE + (1 << 30)
+    # odd width
+    assert lib.dwt2_forward_level(FAKE, 64, 0, 63, 64, B, 64, 0, B + 4096, B + 8192,
+                                  B + 12288, 64, 0, 0, 0, -1, None) == _lib.ERR_INVALID_ARG
+    # output overlaps input
+    assert lib.dwt2_forward_level(FAKE, 64, 0, 64, 64, FAKE + 4, 64, 0, B, B + 8192,
+                                  B + 16384, 64, 0, 0, 0, -1, None) == _lib.ERR_INVALID_ARG
+    # tile id out of range
+    assert lib.dwt2_forward_level(FAKE, 64, 0, 64, 64, B, 64, 0, B + 8192, B + 16384,
+                                  B + 24576, 64, 0, 0, 0, 1000, None) == _lib.ERR_UNSUPPORTED
+    # LL of a third dtype (F16 image, BF16 LL)
+    assert lib.dwt2_inverse_level(B, 32, 2, B + 8192, B + 16384, B + 24576, 32, 1,
+                                  FAKE, 64, 1, 64, 64, 0, 0, -1, None) == _lib.ERR_INVALID_ARG
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    x = torch.zeros(8, 8)
+    with pytest.raises(ValueError):
+        dwt.forward(x)
