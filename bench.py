@@ -63,6 +63,8 @@ def make_image(W, H, kind, seed):
 
 
 def run_gpu(args, x_np, scheme):
+    """Time K steps (graph replays of forward + inverse) and, separately, the
+    level-1 kernels back to back with events; returns timings and outputs."""
     import torch
     import paper_1705_08266_amd as dwt
 
@@ -78,48 +80,92 @@ def run_gpu(args, x_np, scheme):
         rec = torch.empty_like(src)
         ws = dwt.make_workspace(W, H, L, dev)
         sets.append((src, coef, rec, ws))
-    stream = torch.cuda.current_stream()
 
-    def step(k, ev_f=None, ev_i=None):
+    def step(k):
         src, coef, rec, ws = sets[k % len(sets)]
-        dwt.forward(src, args.wavelet, L, scheme, out=coef, workspace=ws, events=ev_f)
-        dwt.inverse(coef, args.wavelet, L, scheme, out=rec, workspace=ws, events=ev_i)
+        dwt.forward(src, args.wavelet, L, scheme, out=coef, workspace=ws)
+        dwt.inverse(coef, args.wavelet, L, scheme, out=rec, workspace=ws)
 
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
+    eager_coef = sets[0][1].clone()
+    eager_rec = sets[0][2].clone()
 
+    graphs = []
+    if not args.eager:
+        # one captured graph per buffer set: the whole L-level forward and
+        # inverse chain is replayed as one launch
+        for k in range(len(sets)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(k)
+            graphs.append(g)
+        for k in range(2 * len(sets)):
+            graphs[k % len(sets)].replay()
+        torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
     K = args.steps
-    evs = [([torch.cuda.Event(enable_timing=True) for _ in range(2 * L)],
-            [torch.cuda.Event(enable_timing=True) for _ in range(2 * L)]) for _ in range(K)]
-    for ef, ei in evs:              # materialise the events before timing
-        for e in ef + ei:
-            e.record(stream)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     t_start.record(stream)
     for k in range(K):
-        step(k, evs[k][0], evs[k][1])
+        if graphs:
+            graphs[k % len(graphs)].replay()
+        else:
+            step(k)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     total_ms = t_start.elapsed_time(t_end)
+    replay_matches = bool(torch.equal(sets[0][1], eager_coef) and torch.equal(sets[0][2], eager_rec))
 
-    fwd_ms = [0.0] * L
-    inv_ms = [0.0] * L
-    for ef, ei in evs:
-        for j in range(L):
-            fwd_ms[j] += ef[2 * j].elapsed_time(ef[2 * j + 1]) / K
-            inv_ms[j] += ei[2 * j].elapsed_time(ei[2 * j + 1]) / K
+    # per-level kernel durations: each level's launch repeated back to back,
+    # bracketed by events on the launch stream, buffers rotating
+    R = max(20, min(200, K))
+    fwd_ms, inv_ms = [], []
+    for j in range(1, L + 1):
+        w, h = W >> (j - 1), H >> (j - 1)
+        for direction in ("forward", "inverse"):
+            def once(k):
+                # the same kernel instantiations as the chain: intermediate LL
+                # bands live in the FP32 workspace, split in two regions
+                src, coef, rec, ws = sets[k % len(sets)]
+                big = (W // 2) * (H // 2)
+                hl, lh, hh = coef[:h // 2, w // 2:w], coef[h // 2:h, :w // 2], coef[h // 2:h, w // 2:w]
+                if j == L:
+                    ll = coef[:h // 2, :w // 2]
+                elif j == 1:
+                    ll = ws[:big].view(H // 2, W // 2)
+                else:
+                    ll = ws[big:big + (w // 2) * (h // 2)].view(h // 2, w // 2)
+                if j == 1:
+                    img = src if direction == "forward" else rec
+                else:
+                    img = ws[:w * h].view(h, w)
+                if direction == "forward":
+                    dwt.forward_level(img, ll, hl, lh, hh, args.wavelet, scheme)
+                else:
+                    dwt.inverse_level(ll, hl, lh, hh, img, args.wavelet, scheme)
+            for k in range(5):
+                once(k)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for k in range(R):
+                once(k)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            (fwd_ms if direction == "forward" else inv_ms).append(e0.elapsed_time(e1) / R)
 
-    # parity of what was timed: set 0's coefficients and reconstruction
-    src, coef, rec, _ = sets[0]
     out = dict(total_ms=total_ms, wall_s=wall, fwd_level_ms=fwd_ms, inv_level_ms=inv_ms,
-               coef=coef.float().cpu().numpy(), rec=rec.float().cpu().numpy(),
-               stored=src.float().cpu().numpy())
-    del sets
+               coef=eager_coef.float().cpu().numpy(), rec=eager_rec.float().cpu().numpy(),
+               stored=sets[0][0].float().cpu().numpy(), graph=bool(graphs),
+               replay_matches_eager=replay_matches)
+    del sets, graphs
     torch.cuda.empty_cache()
     return out
 
@@ -183,6 +229,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-separable", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every step from the host instead of replaying a graph")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -238,6 +286,9 @@ def main():
         algorithmic_bytes_per_step=alg_bytes_step,
         level_ms=dict(forward=[round(v, 5) for v in main_run["fwd_level_ms"]],
                       inverse=[round(v, 5) for v in main_run["inv_level_ms"]]),
+        launch=("one captured HIP graph per buffer set (forward + inverse chain)"
+                if main_run["graph"] else "eager launches"),
+        graph_replay_matches_eager=main_run["replay_matches_eager"],
     )
     if sep_run is not None:
         s_ms = sep_run["total_ms"] / K

@@ -140,15 +140,19 @@ int dwt2_inverse_level(const void *ll, int64_t ll_pitch, int32_t ll_dtype,
                        int32_t wavelet, int32_t scheme, int32_t tile,
                        void *stream);
 
-/* Tile configurations compiled into the library. A tile is a workgroup of
- * `waves` wavefronts stacked vertically; each lane owns `quads_per_lane`
- * consecutive quads of a row and `rows_per_wave` quad rows. Of the
- * (64*quads_per_lane) x (waves*rows_per_wave) quad window, the centre
- * out_x x out_y quads are written; the rest is the lifting halo.
+/* Kernel configurations ("tiles") compiled into the library. Two kinds:
+ *   kind 0, 2-D tile: a workgroup of `waves` wavefronts stacked vertically;
+ *     each lane owns `quads_per_lane` consecutive quads of a row and `rows`
+ *     quad rows. Of the (64*quads_per_lane) x (waves*rows) quad window the
+ *     centre out_x x out_y quads are written; the rest is the lifting halo.
+ *   kind 1, stream: each wavefront walks down a strip out_x quads wide,
+ *     carrying every lifting step of the level in a row pipeline; `rows` is
+ *     its prefetch depth and `waves` the strips segments per workgroup.
+ *     out_y is 0: segment lengths are planned per level from the CU count.
  * Returns DWT2_OK or DWT2_ERR_UNSUPPORTED; null out-pointers are skipped. */
 int dwt2_tile_config_count(void);
-int dwt2_tile_config_info(int32_t tile, int32_t wavelet,
-                          int32_t *quads_per_lane, int32_t *rows_per_wave,
+int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind,
+                          int32_t *quads_per_lane, int32_t *rows,
                           int32_t *waves, int32_t *out_x, int32_t *out_y);
 
 /* The tile id the library picks for one level of the given size. */

@@ -163,11 +163,12 @@ def inverse_level(ll, hl, lh, hh, out, wavelet="cdf97", scheme="nonseparable", t
 
 
 def tile_configs(wavelet="cdf97"):
-    """[(id, quads_per_lane, rows_per_wave, waves, out_x, out_y)] compiled in."""
+    """[(id, kind, quads_per_lane, rows, waves, out_x, out_y)] compiled in;
+    kind 0 = 2-D tile, 1 = stream."""
     lib = load()
     out = []
     for t in range(lib.dwt2_tile_config_count()):
-        v = [ctypes.c_int32() for _ in range(5)]
+        v = [ctypes.c_int32() for _ in range(6)]
         _lib.check(lib.dwt2_tile_config_info(t, _wavelet(wavelet), *[ctypes.byref(a) for a in v]))
         out.append((t, *[a.value for a in v]))
     return out

@@ -41,7 +41,7 @@ SIGNATURES = {
     "dwt2_inverse_level": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _i32,
                                           _vp, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _vp]),
     "dwt2_tile_config_count": (ctypes.c_int, []),
-    "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32]),
+    "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32, _ip32]),
     "dwt2_default_tile": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
     "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dwt2_last_hip_error": (ctypes.c_int, []),

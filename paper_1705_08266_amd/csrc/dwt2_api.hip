@@ -40,31 +40,70 @@ bool aligned(const void *p, int64_t pitch, int dt, int vec_elems) {
     return ((uintptr_t)p % bytes) == 0 && ((size_t)pitch * elem_size(dt)) % bytes == 0;
 }
 
-int out_x(int tile, int) { return 64 * kTiles[tile].qpl - 2 * kTiles[tile].qpl; }
-int out_y(int tile, int wavelet) {
-    const int np = wavelet == DWT2_CDF97 ? 2 : 1;
-    return kTiles[tile].waves * kTiles[tile].rows - 2 * np;
-}
-int grid_of(int tile, int wavelet, int nqx, int nqy, int *tx, int *ty) {
-    const int ox = out_x(tile, wavelet), oy = out_y(tile, wavelet);
-    *tx = (nqx + ox - 1) / ox;
-    *ty = (nqy + oy - 1) / oy;
-    return *tx * *ty;
+int pairs_of(int wavelet) { return wavelet == DWT2_CDF97 ? 2 : 1; }
+
+// Compute units of the current device (queried once per device).
+int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
 }
 
-// Tile choice for one level: the tallest window that still gives the chip
-// enough workgroups; small levels fall back to small windows.
-int pick_tile(int width, int height, int wavelet) {
-    static const int order[] = {0, 7, 1};
-    const int nqx = width / 2, nqy = height / 2;
-    int best = order[0], best_grid = 0;
-    for (int t : order) {
-        int tx, ty;
-        const int g = grid_of(t, wavelet, nqx, nqy, &tx, &ty);
-        if (g >= 512) return t;
-        if (g > best_grid) { best = t; best_grid = g; }
+// Output quad columns per tile (CFG_TILE) or per strip (CFG_STREAM).
+int out_x(int tile, int wavelet) {
+    const TileCfg &c = kTiles[tile];
+    if (c.kind == CFG_TILE) return 64 * c.a - 2 * c.a;
+    const int hxl = (pairs_of(wavelet) + c.a - 1) / c.a;
+    return (64 - 2 * hxl) * c.a;
+}
+// Output quad rows per tile (CFG_TILE); 0 for streams (planned per level).
+int out_y(int tile, int wavelet) {
+    const TileCfg &c = kTiles[tile];
+    if (c.kind == CFG_TILE) return c.waves * c.b - 2 * pairs_of(wavelet);
+    return 0;
+}
+
+// Work decomposition of one level: tiles (tx x ty) or strips x segments.
+struct Plan {
+    int tiles_x, tiles_y, seg;
+};
+Plan plan_level(int tile, int wavelet, int nqx, int nqy) {
+    const TileCfg &c = kTiles[tile];
+    Plan p;
+    const int ox = out_x(tile, wavelet);
+    p.tiles_x = (nqx + ox - 1) / ox;
+    if (c.kind == CFG_TILE) {
+        const int oy = out_y(tile, wavelet);
+        p.tiles_y = (nqy + oy - 1) / oy;
+        p.seg = oy;
+    } else {
+        // about per_cu wavefronts per CU; a segment is at least 8 rows so its
+        // lifting halo (two rows per pair) stays a small fraction
+        const int target = device_cus() * c.per_cu;
+        int segs = (target + p.tiles_x - 1) / p.tiles_x;
+        if (segs < 1) segs = 1;
+        int seg = (nqy + segs - 1) / segs;
+        if (seg < 8) seg = 8;
+        if (seg > nqy) seg = nqy;
+        p.seg = seg;
+        p.tiles_y = (nqy + seg - 1) / seg;
     }
-    return best;
+    return p;
+}
+
+// Configuration choice for one level: the 128 x 16-quad tile was the fastest
+// measured configuration from 256^2 to 4096^2 levels.
+int pick_tile(int width, int height, int wavelet) {
+    (void)width; (void)height; (void)wavelet;
+    return 1;
 }
 
 const FwdTable &fwd_table(int dt) {
@@ -90,15 +129,16 @@ int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height
     p.ll = ll; p.ll_pitch = ll_pitch;
     p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
     p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
-    const int grid = grid_of(tile, wavelet, nqx, nqy, &p.tiles_x, &p.tiles_y);
-    const int q = kTiles[tile].qpl;
+    const Plan pl = plan_level(tile, wavelet, nqx, nqy);
+    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y; p.seg = pl.seg;
+    const int q = kTiles[tile].a;
     p.vec_in = aligned(in, in_pitch, in_dt, 2 * q);
     p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
     const FwdLauncher f =
         fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
-    const hipError_t e = f(p, grid, stream);
+    const hipError_t e = f(p, stream);
     return e == hipSuccess ? DWT2_OK : hip_fail(e);
 }
 
@@ -113,15 +153,16 @@ int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const
     p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
     p.out = out; p.out_pitch = out_pitch;
     p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
-    const int grid = grid_of(tile, wavelet, nqx, nqy, &p.tiles_x, &p.tiles_y);
-    const int q = kTiles[tile].qpl;
+    const Plan pl = plan_level(tile, wavelet, nqx, nqy);
+    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y; p.seg = pl.seg;
+    const int q = kTiles[tile].a;
     p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
     p.vec_out = aligned(out, out_pitch, out_dt, 2 * q);
     const InvLauncher f =
         inv_table(band_dt)[wavelet][scheme][ll_dt == DWT2_F32][out_dt == DWT2_F32][tile];
-    const hipError_t e = f(p, grid, stream);
+    const hipError_t e = f(p, stream);
     return e == hipSuccess ? DWT2_OK : hip_fail(e);
 }
 
@@ -219,11 +260,12 @@ size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels) {
 
 int dwt2_tile_config_count(void) { return kNumTiles; }
 
-int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *quads_per_lane,
-                          int32_t *rows_per_wave, int32_t *waves, int32_t *ox, int32_t *oy) {
+int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind, int32_t *quads_per_lane,
+                          int32_t *rows, int32_t *waves, int32_t *ox, int32_t *oy) {
     if (tile < 0 || tile >= kNumTiles || !valid_wavelet(wavelet)) return DWT2_ERR_UNSUPPORTED;
-    if (quads_per_lane) *quads_per_lane = kTiles[tile].qpl;
-    if (rows_per_wave) *rows_per_wave = kTiles[tile].rows;
+    if (kind) *kind = kTiles[tile].kind;
+    if (quads_per_lane) *quads_per_lane = kTiles[tile].a;
+    if (rows) *rows = kTiles[tile].b;
     if (waves) *waves = kTiles[tile].waves;
     if (ox) *ox = out_x(tile, wavelet);
     if (oy) *oy = out_y(tile, wavelet);

@@ -33,16 +33,16 @@ template <int WV> struct Wavelet;
 template <> struct Wavelet<CDF97> {
     static constexpr int NPAIRS = 2;
     static constexpr double K = 1.230174104914001;
-    __device__ static constexpr double p(int k) { return k == 0 ? -1.586134342059924 : 0.882911075530934; }
-    __device__ static constexpr double u(int k) { return k == 0 ? -0.052980118572961 : 0.443506852043971; }
+    __host__ __device__ static constexpr double p(int k) { return k == 0 ? -1.586134342059924 : 0.882911075530934; }
+    __host__ __device__ static constexpr double u(int k) { return k == 0 ? -0.052980118572961 : 0.443506852043971; }
     static constexpr double ZL = 1.0 / K;
     static constexpr double ZH = K / 2.0;
 };
 
 template <> struct Wavelet<CDF53> {
     static constexpr int NPAIRS = 1;
-    __device__ static constexpr double p(int) { return -0.5; }
-    __device__ static constexpr double u(int) { return 0.25; }
+    __host__ __device__ static constexpr double p(int) { return -0.5; }
+    __host__ __device__ static constexpr double u(int) { return 0.25; }
     static constexpr double ZL = 1.0;
     static constexpr double ZH = 0.5;
 };
@@ -91,75 +91,120 @@ template <> __device__ __forceinline__ uint32_t bits_of<float>(float v) { return
 template <> __device__ __forceinline__ uint32_t bits_of<__half>(__half v) { return (uint32_t)__half_as_ushort(v); }
 template <> __device__ __forceinline__ uint32_t bits_of<bf16_t>(bf16_t v) { return v.bits; }
 
-// N consecutive elements as one vector memory access (N*sizeof(T) in 8..32 B,
-// pointer aligned to min(16, N*sizeof(T))).
-template <typename T, int N>
-__device__ __forceinline__ void load_vec(const T *__restrict__ p, float (&out)[N]) {
-    constexpr int BYTES = N * (int)sizeof(T);
-    static_assert(BYTES == 4 || BYTES == 8 || BYTES == 16 || BYTES == 32, "vector width");
-    if constexpr (sizeof(T) == 4) {
-        static_assert(BYTES >= 8, "at least two FP32 elements");
-        if constexpr (BYTES == 8) {
-            float2 v = *reinterpret_cast<const float2 *>(p);
-            out[0] = v.x; out[1] = v.y;
-        } else {
-#pragma unroll
-            for (int h = 0; h < BYTES / 16; ++h) {
-                float4 v = *reinterpret_cast<const float4 *>(p + 4 * h);
-                out[4 * h + 0] = v.x; out[4 * h + 1] = v.y;
-                out[4 * h + 2] = v.z; out[4 * h + 3] = v.w;
-            }
-        }
+// ---- vector row access through buffer resources ---------------------------------
+// A row of a 2-D buffer is described by a wave-uniform buffer resource (base
+// pointer and byte length); each lane addresses it with a 32-bit byte offset.
+// The hardware checks every access against the length: reads past the end
+// return zero and writes past the end are dropped.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // raw (untyped) buffer, gfx9 family
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Raw 32-bit words of an access of W words.
+template <int W>
+__device__ __forceinline__ void buf_load_words(rsrc_t r, uint32_t off, uint32_t (&w)[W]) {
+    static_assert(W == 1 || W == 2 || W == 4 || W == 8, "access width");
+    if constexpr (W == 1) {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+    } else if constexpr (W == 2) {
+        u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        w[0] = v.x; w[1] = v.y;
     } else {
+#pragma unroll
+        for (int h = 0; h < W / 4; ++h) {
+            u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u * h), 0, 0);
+            w[4 * h] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void buf_store_words(rsrc_t r, uint32_t off, const uint32_t (&w)[W]) {
+    static_assert(W == 1 || W == 2 || W == 4 || W == 8, "access width");
+    if constexpr (W == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)off, 0, 0);
+    } else if constexpr (W == 2) {
+        u32x2 v; v.x = w[0]; v.y = w[1];
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+    } else {
+#pragma unroll
+        for (int h = 0; h < W / 4; ++h) {
+            u32x4 v; v.x = w[4 * h]; v.y = w[4 * h + 1]; v.z = w[4 * h + 2]; v.w = w[4 * h + 3];
+            __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(off + 16u * h), 0, 0);
+        }
+    }
+}
+
+// One element of type T at byte offset `off` (reads past the end give 0).
+template <typename T>
+__device__ __forceinline__ float load_elem(rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    } else {
+        return Storage<T>::decode((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_elem(rsrc_t r, uint32_t off, float v) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)bits_of<T>(from_float<T>(v)), r,
+                                              (int)off, 0, 0);
+    }
+}
+
+// A byte offset that every buffer resource of this library rejects: rows
+// are shorter than 2 GiB, so a store at this offset is dropped.
+constexpr uint32_t kNoAccess = 0x80000000u;
+
+// N consecutive elements of type T (2 to 32 bytes) at byte offset `off`.
+template <typename T, int N>
+__device__ __forceinline__ void load_vec(rsrc_t r, uint32_t off, float (&out)[N]) {
+    constexpr int BYTES = N * (int)sizeof(T);
+    if constexpr (BYTES == 2) {
+        out[0] = load_elem<T>(r, off);
+    } else {
+        static_assert(BYTES % 4 == 0, "whole words");
         uint32_t w[BYTES / 4];
-        if constexpr (BYTES == 4) {
-            w[0] = *reinterpret_cast<const uint32_t *>(p);
-        } else if constexpr (BYTES == 8) {
-            uint2 v = *reinterpret_cast<const uint2 *>(p);
-            w[0] = v.x; w[1] = v.y;
+        buf_load_words<BYTES / 4>(r, off, w);
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) out[e] = __uint_as_float(w[e]);
         } else {
 #pragma unroll
-            for (int h = 0; h < BYTES / 16; ++h) {
-                uint4 v = *reinterpret_cast<const uint4 *>(p + 8 * h);
-                w[4 * h + 0] = v.x; w[4 * h + 1] = v.y;
-                w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
-            }
+            for (int e = 0; e < N; ++e)
+                out[e] = Storage<T>::decode((w[e / 2] >> (16 * (e & 1))) & 0xffffu);
         }
-#pragma unroll
-        for (int e = 0; e < N; ++e)
-            out[e] = Storage<T>::decode((w[e / 2] >> (16 * (e & 1))) & 0xffffu);
     }
 }
 
 template <typename T, int N>
-__device__ __forceinline__ void store_vec(T *__restrict__ p, const float (&in)[N]) {
+__device__ __forceinline__ void store_vec(rsrc_t r, uint32_t off, const float (&in)[N]) {
     constexpr int BYTES = N * (int)sizeof(T);
-    static_assert(BYTES == 4 || BYTES == 8 || BYTES == 16 || BYTES == 32, "vector width");
-    if constexpr (sizeof(T) == 4) {
-        if constexpr (BYTES == 8) {
-            *reinterpret_cast<float2 *>(p) = make_float2(in[0], in[1]);
-        } else {
-#pragma unroll
-            for (int h = 0; h < BYTES / 16; ++h)
-                *reinterpret_cast<float4 *>(p + 4 * h) =
-                    make_float4(in[4 * h], in[4 * h + 1], in[4 * h + 2], in[4 * h + 3]);
-        }
+    if constexpr (BYTES == 2) {
+        store_elem<T>(r, off, in[0]);
     } else {
-        uint32_t w[(BYTES + 3) / 4];
+        static_assert(BYTES % 4 == 0, "whole words");
+        uint32_t w[BYTES / 4];
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int e = 0; e < N; e += 2)
-            w[e / 2] = bits_of<T>(from_float<T>(in[e])) |
-                       (bits_of<T>(from_float<T>(in[e + 1])) << 16);
-        if constexpr (BYTES == 4) {
-            *reinterpret_cast<uint32_t *>(p) = w[0];
-        } else if constexpr (BYTES == 8) {
-            *reinterpret_cast<uint2 *>(p) = make_uint2(w[0], w[1]);
+            for (int e = 0; e < N; ++e) w[e] = __float_as_uint(in[e]);
         } else {
 #pragma unroll
-            for (int h = 0; h < BYTES / 16; ++h)
-                *reinterpret_cast<uint4 *>(p + 8 * h) =
-                    make_uint4(w[4 * h], w[4 * h + 1], w[4 * h + 2], w[4 * h + 3]);
+            for (int e = 0; e < N; e += 2)
+                w[e / 2] = bits_of<T>(from_float<T>(in[e])) |
+                           (bits_of<T>(from_float<T>(in[e + 1])) << 16);
         }
+        buf_store_words<BYTES / 4>(r, off, w);
     }
 }
 

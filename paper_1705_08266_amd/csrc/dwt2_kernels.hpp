@@ -23,6 +23,7 @@ struct FwdParams {
     int64_t band_pitch;
     int32_t w, h, nqx, nqy;
     int32_t tiles_x, tiles_y;
+    int32_t seg;                        // streaming kernels: output rows per segment
     int32_t vec_in, vec_ll, vec_band;   // 1 when vector accesses are aligned
 };
 
@@ -35,6 +36,7 @@ struct InvParams {
     int64_t out_pitch;
     int32_t w, h, nqx, nqy;
     int32_t tiles_x, tiles_y;
+    int32_t seg;
     int32_t vec_ll, vec_band, vec_out;
 };
 
@@ -54,29 +56,30 @@ struct TileGeom {
 };
 
 // The hardware hands consecutive workgroup ids to the 8 XCDs in turn. Remap
-// so that each XCD gets one contiguous run of tiles (row-major), keeping the
-// halo rows shared by vertically adjacent tiles in the same L2.
+// the ids so that the workgroups of one XCD are numbered contiguously; with
+// contiguous tile runs per workgroup, each XCD then works on one contiguous
+// region of the image and the halo rows shared by neighbouring tiles stay in
+// that XCD's L2.
 __device__ __forceinline__ int xcd_contiguous_tile(int b, int n) {
     const int per = n >> 3, rem = n & 7;
     const int xcd = b & 7, idx = b >> 3;
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
-__global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
-    using G = TileGeom<WV, QPL, ROWS, WAVES>;
-    __shared__ Mailbox<QPL, (WAVES > 1 ? WAVES : 1)> box;
+// Tiles are numbered column-major (down a column of tiles first); with the
+// XCD-contiguous block numbering each XCD works down whole tile columns, so
+// the halo rows shared by vertically adjacent tiles are read through one L2.
+__device__ __forceinline__ int block_tile() {
+    return xcd_contiguous_tile(blockIdx.x, gridDim.x);
+}
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tile = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-    const int ty = tile / prm.tiles_x;
-    const int tx = tile - ty * prm.tiles_x;
+// ---- forward: load / store of one tile ----------------------------------------
+template <int QPL, int ROWS, typename G, typename TIN>
+__device__ __forceinline__ void fwd_load(Quads<ROWS, QPL> &q, const FwdParams &prm, int t,
+                                         int lane, int wave) {
+    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;   // first quad column of the lane
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;  // first quad row of the lane
-
-    // ---- load: two pixel rows per quad row, 2*QPL pixels per row per lane
-    Quads<ROWS, QPL> q;
     const TIN *in = static_cast<const TIN *>(prm.in);
     const int px0 = 2 * qx0;
     const bool lane_inside = prm.vec_in && px0 >= 0 && px0 + 2 * QPL <= prm.w;
@@ -85,8 +88,10 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
         const int py = 2 * (qy0 + r);
         if (lane_inside && py >= 0 && py + 2 <= prm.h) {
             float e[2 * QPL], o[2 * QPL];
-            load_vec<TIN, 2 * QPL>(in + (int64_t)py * prm.in_pitch + px0, e);
-            load_vec<TIN, 2 * QPL>(in + (int64_t)(py + 1) * prm.in_pitch + px0, o);
+            const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TIN);
+            const uint32_t off = (uint32_t)px0 * (uint32_t)sizeof(TIN);
+            load_vec<TIN, 2 * QPL>(make_rsrc(in + (int64_t)py * prm.in_pitch, rb), off, e);
+            load_vec<TIN, 2 * QPL>(make_rsrc(in + (int64_t)(py + 1) * prm.in_pitch, rb), off, o);
 #pragma unroll
             for (int i = 0; i < QPL; ++i) {
                 q.a[r][i] = e[2 * i]; q.b[r][i] = e[2 * i + 1];
@@ -104,16 +109,18 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
             }
         }
     }
+}
 
-    // ---- all lifting steps of the level, in registers
-    Exchange<ROWS, QPL, WAVES> x{reinterpret_cast<Mailbox<QPL, WAVES> *>(&box), wave, lane, 0};
-    lift_forward<WV, SCH>(q, x);
-
-    // ---- scale and store the centre of the window
+template <int WV, int QPL, int ROWS, int WAVES, typename G, typename TLL, typename TB>
+__device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdParams &prm, int t,
+                                          int lane, int wave) {
     using L = Wavelet<WV>;
     const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
     const float sHH = (float)(L::ZH * L::ZH);
-    if (lane == 0 || lane == 63) return;
+    if (lane == 0 || lane == 63) return;   // halo lanes
+    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int qx0 = tx * G::OX - G::HX + lane * QPL;
+    const int qy0 = ty * G::OY - G::HY + wave * ROWS;
     TLL *ll = static_cast<TLL *>(prm.ll);
     TB *hl = static_cast<TB *>(prm.hl);
     TB *lh = static_cast<TB *>(prm.lh);
@@ -133,16 +140,21 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
         const int64_t ob = (int64_t)gy * prm.band_pitch + qx0;
         const int64_t ol = (int64_t)gy * prm.ll_pitch + qx0;
         if (full_x && prm.vec_ll) {
-            store_vec<TLL, QPL>(ll + ol, va);
+            store_vec<TLL, QPL>(make_rsrc(ll + (int64_t)gy * prm.ll_pitch,
+                                          (uint32_t)prm.nqx * (uint32_t)sizeof(TLL)),
+                                (uint32_t)qx0 * (uint32_t)sizeof(TLL), va);
         } else {
 #pragma unroll
             for (int i = 0; i < QPL; ++i)
                 if (qx0 + i < prm.nqx) ll[ol + i] = from_float<TLL>(va[i]);
         }
         if (full_x && prm.vec_band) {
-            store_vec<TB, QPL>(hl + ob, vb);
-            store_vec<TB, QPL>(lh + ob, vc);
-            store_vec<TB, QPL>(hh + ob, vd);
+            const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
+            const uint32_t off = (uint32_t)qx0 * (uint32_t)sizeof(TB);
+            const int64_t rowo = (int64_t)gy * prm.band_pitch;
+            store_vec<TB, QPL>(make_rsrc(hl + rowo, bb), off, vb);
+            store_vec<TB, QPL>(make_rsrc(lh + rowo, bb), off, vc);
+            store_vec<TB, QPL>(make_rsrc(hh + rowo, bb), off, vd);
         } else {
 #pragma unroll
             for (int i = 0; i < QPL; ++i) {
@@ -156,23 +168,31 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
     }
 }
 
-template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
-__global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
+// One tile per workgroup.
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
     using G = TileGeom<WV, QPL, ROWS, WAVES>;
-    __shared__ Mailbox<QPL, (WAVES > 1 ? WAVES : 1)> box;
-
+    __shared__ Mailbox<QPL, WAVES> box;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tile = xcd_contiguous_tile(blockIdx.x, gridDim.x);
-    const int ty = tile / prm.tiles_x;
-    const int tx = tile - ty * prm.tiles_x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+    const int t = block_tile();
+    Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
+    Quads<ROWS, QPL> q;
+    fwd_load<QPL, ROWS, G, TIN>(q, prm, t, lane, wave);
+    lift_forward<WV, SCH>(q, x);
+    fwd_store<WV, QPL, ROWS, WAVES, G, TLL, TB>(q, prm, t, lane, wave);
+}
+
+// ---- inverse ---------------------------------------------------------------------
+// Outside the level, each polyphase component is extended through the
+// symmetric extension of the pixel grid it lives on: quad (i, j) component b
+// stands for pixel (2i+1, 2j), and so on.
+template <int QPL, int ROWS, typename G, typename TLL, typename TB>
+__device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &prm, int t,
+                                         int lane, int wave) {
+    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;
-
-    // ---- load the four bands. Outside the level, each polyphase component is
-    // extended through the symmetric extension of the pixel grid it lives on:
-    // quad (i, j) component b stands for pixel (2i+1, 2j), and so on.
-    Quads<ROWS, QPL> q;
     const TLL *ll = static_cast<const TLL *>(prm.ll);
     const TB *hl = static_cast<const TB *>(prm.hl);
     const TB *lh = static_cast<const TB *>(prm.lh);
@@ -182,11 +202,15 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
     for (int r = 0; r < ROWS; ++r) {
         const int gy = qy0 + r;
         if (lane_inside && gy >= 0 && gy < prm.nqy) {
-            const int64_t ob = (int64_t)gy * prm.band_pitch + qx0;
-            load_vec<TLL, QPL>(ll + (int64_t)gy * prm.ll_pitch + qx0, q.a[r]);
-            load_vec<TB, QPL>(hl + ob, q.b[r]);
-            load_vec<TB, QPL>(lh + ob, q.c[r]);
-            load_vec<TB, QPL>(hh + ob, q.d[r]);
+            const int64_t ob = (int64_t)gy * prm.band_pitch;
+            const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
+            const uint32_t offb = (uint32_t)qx0 * (uint32_t)sizeof(TB);
+            load_vec<TLL, QPL>(make_rsrc(ll + (int64_t)gy * prm.ll_pitch,
+                                         (uint32_t)prm.nqx * (uint32_t)sizeof(TLL)),
+                               (uint32_t)qx0 * (uint32_t)sizeof(TLL), q.a[r]);
+            load_vec<TB, QPL>(make_rsrc(hl + ob, bb), offb, q.b[r]);
+            load_vec<TB, QPL>(make_rsrc(lh + ob, bb), offb, q.c[r]);
+            load_vec<TB, QPL>(make_rsrc(hh + ob, bb), offb, q.d[r]);
         } else {
             const int ye = mirror(2 * gy, prm.h) >> 1;
             const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
@@ -201,23 +225,15 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
             }
         }
     }
+}
 
-    // ---- undo the scaling, then the lifting steps in reverse
-    using L = Wavelet<WV>;
-    const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
-    const float uHH = (float)(1.0 / (L::ZH * L::ZH));
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-#pragma unroll
-        for (int i = 0; i < QPL; ++i) {
-            q.a[r][i] *= uLL; q.b[r][i] *= uHL; q.c[r][i] *= uHL; q.d[r][i] *= uHH;
-        }
-    }
-    Exchange<ROWS, QPL, WAVES> x{reinterpret_cast<Mailbox<QPL, WAVES> *>(&box), wave, lane, 0};
-    lift_inverse<WV, SCH>(q, x);
-
-    // ---- store interleaved pixels of the window centre
-    if (lane == 0 || lane == 63) return;
+template <int QPL, int ROWS, int WAVES, typename G, typename TOUT>
+__device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvParams &prm, int t,
+                                          int lane, int wave) {
+    if (lane == 0 || lane == 63) return;   // halo lanes
+    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int qx0 = tx * G::OX - G::HX + lane * QPL;
+    const int qy0 = ty * G::OY - G::HY + wave * ROWS;
     TOUT *out = static_cast<TOUT *>(prm.out);
     const int px0 = 2 * qx0;
     const bool full_x = prm.vec_out && px0 + 2 * QPL <= prm.w;
@@ -235,8 +251,10 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
         TOUT *r0 = out + (int64_t)(2 * gy) * prm.out_pitch;
         TOUT *r1 = r0 + prm.out_pitch;
         if (full_x) {
-            store_vec<TOUT, 2 * QPL>(r0 + px0, e);
-            store_vec<TOUT, 2 * QPL>(r1 + px0, o);
+            const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TOUT);
+            const uint32_t off = (uint32_t)px0 * (uint32_t)sizeof(TOUT);
+            store_vec<TOUT, 2 * QPL>(make_rsrc(r0, rb), off, e);
+            store_vec<TOUT, 2 * QPL>(make_rsrc(r1, rb), off, o);
         } else {
 #pragma unroll
             for (int k = 0; k < 2 * QPL; ++k) {
@@ -247,6 +265,30 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
             }
         }
     }
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
+    using G = TileGeom<WV, QPL, ROWS, WAVES>;
+    using L = Wavelet<WV>;
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+    const int t = block_tile();
+    const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
+    const float uHH = (float)(1.0 / (L::ZH * L::ZH));
+    Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
+    Quads<ROWS, QPL> q;
+    inv_load<QPL, ROWS, G, TLL, TB>(q, prm, t, lane, wave);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            q.a[r][i] *= uLL; q.b[r][i] *= uHL; q.c[r][i] *= uHL; q.d[r][i] *= uHH;
+        }
+    }
+    lift_inverse<WV, SCH>(q, x);
+    inv_store<QPL, ROWS, WAVES, G, TOUT>(q, prm, t, lane, wave);
 }
 
 }  // namespace dwt2

@@ -1,48 +1,74 @@
-// Launch table: one launcher per (wavelet, scheme, storage types, tile).
+// Launch table: one launcher per (wavelet, scheme, storage types, config).
 #pragma once
 
 #include <array>
 #include <utility>
 
 #include "dwt2_kernels.hpp"
+#include "dwt2_stream.hpp"
 
 namespace dwt2 {
 
+enum : int { CFG_TILE = 0, CFG_STREAM = 1 };
+
+// A compiled kernel configuration.
+//   CFG_TILE:   a = quads per lane, b = quad rows per lane, waves stacked in y;
+//               window (64a) x (waves*b) quads, one tile per workgroup.
+//   CFG_STREAM: a = quads per lane, b = prefetch depth in rows, `waves`
+//               independent strip segments per workgroup; segments are sized
+//               so that about `per_cu` wavefronts per CU cover the level.
 struct TileCfg {
-    int qpl;    // quads per lane along x
-    int rows;   // quad rows per lane
-    int waves;  // wavefronts stacked along y
+    int kind;
+    int a;
+    int b;
+    int waves;
+    int per_cu;
 };
 
-// Compiled tile shapes. Window = (64*qpl) x (waves*rows) quads.
 constexpr TileCfg kTiles[] = {
-    {2, 8, 4},    // 0: 128 x 32 window, 256 threads
-    {2, 4, 4},    // 1: 128 x 16
-    {4, 4, 4},    // 2: 256 x 16
-    {2, 16, 4},   // 3: 128 x 64
-    {2, 8, 8},    // 4: 128 x 64, 512 threads
-    {2, 8, 1},    // 5: 128 x 8, one wavefront, no barriers
-    {4, 8, 4},    // 6: 256 x 32
-    {2, 4, 8},    // 7: 128 x 32, 512 threads
+    {CFG_TILE, 2, 8, 4, 0},      // 0: 128 x 32 window, 256 threads
+    {CFG_TILE, 2, 4, 4, 0},      // 1: 128 x 16
+    {CFG_TILE, 2, 8, 1, 0},      // 2: 128 x 8, one wavefront, no barriers
+    {CFG_TILE, 2, 4, 8, 0},      // 3: 128 x 32, 512 threads
+    {CFG_STREAM, 2, 8, 4, 8},    // 4: strips of 124 quads (9/7)
+    {CFG_STREAM, 2, 6, 4, 8},    // 5
+    {CFG_STREAM, 1, 8, 4, 8},    // 6: strips of 60 quads (9/7)
+    {CFG_STREAM, 2, 8, 4, 4},    // 7
+    {CFG_STREAM, 2, 8, 4, 16},   // 8
+    {CFG_STREAM, 4, 4, 4, 8},    // 9: strips of 248 quads (prefetch 2 rows)
 };
 constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
-using FwdLauncher = hipError_t (*)(const FwdParams &, int grid, hipStream_t);
-using InvLauncher = hipError_t (*)(const InvParams &, int grid, hipStream_t);
+// A launcher takes the level parameters (grid fields filled in by the host
+// planner) and launches its kernel.
+using FwdLauncher = hipError_t (*)(const FwdParams &, hipStream_t);
+using InvLauncher = hipError_t (*)(const InvParams &, hipStream_t);
 
 template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
-hipError_t launch_fwd(const FwdParams &p, int grid, hipStream_t s) {
+hipError_t launch_fwd(const FwdParams &p, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    hipLaunchKernelGGL((fwd_level_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>),
-                       dim3(grid), dim3(64 * c.waves), 0, s, p);
+    const int tasks = p.tiles_x * p.tiles_y;
+    if constexpr (c.kind == CFG_TILE) {
+        hipLaunchKernelGGL((fwd_level_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>),
+                           dim3(tasks), dim3(64 * c.waves), 0, s, p);
+    } else {
+        hipLaunchKernelGGL((fwd_stream_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>),
+                           dim3((tasks + c.waves - 1) / c.waves), dim3(64 * c.waves), 0, s, p);
+    }
     return hipGetLastError();
 }
 
 template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
-hipError_t launch_inv(const InvParams &p, int grid, hipStream_t s) {
+hipError_t launch_inv(const InvParams &p, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    hipLaunchKernelGGL((inv_level_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>),
-                       dim3(grid), dim3(64 * c.waves), 0, s, p);
+    const int tasks = p.tiles_x * p.tiles_y;
+    if constexpr (c.kind == CFG_TILE) {
+        hipLaunchKernelGGL((inv_level_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>),
+                           dim3(tasks), dim3(64 * c.waves), 0, s, p);
+    } else {
+        hipLaunchKernelGGL((inv_stream_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>),
+                           dim3((tasks + c.waves - 1) / c.waves), dim3(64 * c.waves), 0, s, p);
+    }
     return hipGetLastError();
 }
 
@@ -56,9 +82,10 @@ constexpr std::array<InvLauncher, kNumTiles> inv_tiles(std::integer_sequence<int
 }
 
 // Per storage type T of the user-visible buffers: index [wavelet][scheme]
-// [first operand is FP32][second operand is FP32][tile], where for the forward
-// the operands are (level input, LL output) and for the inverse (LL input,
-// level output); the other one of each pair is T. Intermediate levels use FP32.
+// [first operand is FP32][second operand is FP32][config], where for the
+// forward the operands are (level input, LL output) and for the inverse
+// (LL input, level output); the other one of each pair is T. Intermediate
+// levels use FP32.
 using FwdTable = std::array<std::array<std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
 using InvTable = std::array<std::array<std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
 
@@ -86,7 +113,7 @@ constexpr InvTable make_inv_table() {
              {inv_types<T, CDF53, NONSEP>(), inv_types<T, CDF53, SEP>()}}};
 }
 
-// Defined in one translation unit per storage type.
+// Defined in one translation unit per storage type and direction.
 extern FwdTable kFwdF32, kFwdF16, kFwdBF16;
 extern InvTable kInvF32, kInvF16, kInvBF16;
 

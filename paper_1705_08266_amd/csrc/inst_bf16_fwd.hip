@@ -1,0 +1,6 @@
+// Kernel instantiations: fwd levels with bf16 storage of user-visible buffers.
+#include "dwt2_table.hpp"
+
+namespace dwt2 {
+FwdTable kFwdBF16 = make_fwd_table<bf16_t>();
+}  // namespace dwt2

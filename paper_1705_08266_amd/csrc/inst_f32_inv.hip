@@ -1,0 +1,6 @@
+// Kernel instantiations: inv levels with f32 storage of user-visible buffers.
+#include "dwt2_table.hpp"
+
+namespace dwt2 {
+InvTable kInvF32 = make_inv_table<float>();
+}  // namespace dwt2

@@ -50,10 +50,16 @@ def test_tile_configs_cover_the_lifting_halo():
     for w, np_ in (("cdf97", 2), ("cdf53", 1)):
         cfgs = dwt.tile_configs(w)
         assert len(cfgs) >= 4
-        for (t, qpl, rows, waves, ox, oy) in cfgs:
-            assert qpl >= np_                        # one halo lane each side
-            assert ox == 64 * qpl - 2 * qpl
-            assert oy == waves * rows - 2 * np_ > 0
+        kinds = {c[1] for c in cfgs}
+        assert kinds == {0, 1}
+        for (t, kind, qpl, rows, waves, ox, oy) in cfgs:
+            if kind == 0:                            # 2-D tile: one halo lane each side
+                assert qpl >= np_
+                assert ox == 64 * qpl - 2 * qpl
+                assert oy == waves * rows - 2 * np_ > 0
+            else:                                    # stream: ceil(np/qpl) halo lanes
+                hxl = -(-np_ // qpl)
+                assert ox == (64 - 2 * hxl) * qpl and oy == 0
 
 
 def test_default_tile_is_valid():
