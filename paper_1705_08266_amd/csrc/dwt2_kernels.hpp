@@ -66,9 +66,10 @@ __device__ __forceinline__ int xcd_contiguous_tile(int b, int n) {
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-// Tiles are numbered column-major (down a column of tiles first); with the
-// XCD-contiguous block numbering each XCD works down whole tile columns, so
-// the halo rows shared by vertically adjacent tiles are read through one L2.
+// Tiles are numbered row-major; with the XCD-contiguous block numbering each
+// XCD sweeps one horizontal band of the level, so the rows it has in flight
+// are few and whole (DRAM page locality), and horizontally adjacent tiles,
+// which share partial cache lines at their edges, meet in the same L2.
 __device__ __forceinline__ int block_tile() {
     return xcd_contiguous_tile(blockIdx.x, gridDim.x);
 }
@@ -77,7 +78,7 @@ __device__ __forceinline__ int block_tile() {
 template <int QPL, int ROWS, typename G, typename TIN>
 __device__ __forceinline__ void fwd_load(Quads<ROWS, QPL> &q, const FwdParams &prm, int t,
                                          int lane, int wave) {
-    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;   // first quad column of the lane
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;  // first quad row of the lane
     const TIN *in = static_cast<const TIN *>(prm.in);
@@ -118,7 +119,7 @@ __device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdPa
     const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
     const float sHH = (float)(L::ZH * L::ZH);
     if (lane == 0 || lane == 63) return;   // halo lanes
-    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;
     TLL *ll = static_cast<TLL *>(prm.ll);
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
 template <int QPL, int ROWS, typename G, typename TLL, typename TB>
 __device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &prm, int t,
                                          int lane, int wave) {
-    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;
     const TLL *ll = static_cast<const TLL *>(prm.ll);
@@ -231,7 +232,7 @@ template <int QPL, int ROWS, int WAVES, typename G, typename TOUT>
 __device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvParams &prm, int t,
                                           int lane, int wave) {
     if (lane == 0 || lane == 63) return;   // halo lanes
-    const int tx = t / prm.tiles_y, ty = t - (t / prm.tiles_y) * prm.tiles_y;
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
     const int qx0 = tx * G::OX - G::HX + lane * QPL;
     const int qy0 = ty * G::OY - G::HY + wave * ROWS;
     TOUT *out = static_cast<TOUT *>(prm.out);

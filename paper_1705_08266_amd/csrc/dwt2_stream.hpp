@@ -514,8 +514,8 @@ __device__ __forceinline__ void stream_segment(int y0, int y_end_out, const IO &
         stream_iters<SL, QPL, D, NS, 0>(ring, saved, y_first + ib, io);
 }
 
-// Each wavefront of the workgroup processes one segment; segments are
-// numbered down a strip first. prm.tiles_x = strips, prm.tiles_y = segments
+// Each wavefront of the workgroup processes one segment; tasks are numbered
+// row-major over (segment row, strip), so each XCD sweeps a horizontal band. prm.tiles_x = strips, prm.tiles_y = segments
 // per strip, prm.seg = output rows per segment.
 template <int WV, int SCH, int QPL, int D, int WAVES, typename TIN, typename TLL, typename TB>
 __global__ __launch_bounds__(64 * WAVES) void fwd_stream_kernel(FwdParams prm) {
@@ -525,8 +525,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_stream_kernel(FwdParams prm) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
     const int task = xcd_contiguous_tile(blockIdx.x, gridDim.x) * WAVES + wave;
     if (task >= prm.tiles_x * prm.tiles_y) return;
-    const int sx = task / prm.tiles_y;
-    const int sy = task - sx * prm.tiles_y;
+    const int sy = task / prm.tiles_x;             // row-major over (segment, strip)
+    const int sx = task - sy * prm.tiles_x;
     const int qx0 = sx * GM::OX + (lane - GM::HXL) * QPL;
     const int y0 = sy * prm.seg;
     const int y_end = min(y0 + prm.seg, prm.nqy);
@@ -552,8 +552,8 @@ __global__ __launch_bounds__(64 * WAVES) void inv_stream_kernel(InvParams prm) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
     const int task = xcd_contiguous_tile(blockIdx.x, gridDim.x) * WAVES + wave;
     if (task >= prm.tiles_x * prm.tiles_y) return;
-    const int sx = task / prm.tiles_y;
-    const int sy = task - sx * prm.tiles_y;
+    const int sy = task / prm.tiles_x;             // row-major over (segment, strip)
+    const int sx = task - sy * prm.tiles_x;
     const int qx0 = sx * GM::OX + (lane - GM::HXL) * QPL;
     const int y0 = sy * prm.seg;
     const int y_end = min(y0 + prm.seg, prm.nqy);
