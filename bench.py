@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--no-separable", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="launch every step from the host instead of replaying a graph")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run 4 device copies of 64 MiB (reference kernel of known "
+                         "traffic for counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +259,14 @@ def main():
     print(f"[bench] {W}x{H} {args.image} {args.dtype} {args.wavelet} L={L} "
           f"{args.scheme}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
           flush=True)
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(16 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     main_run = run_gpu(args, x, args.scheme)
     sep_run = None
     if not args.no_separable and args.scheme != "separable":

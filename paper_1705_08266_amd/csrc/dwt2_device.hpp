@@ -73,7 +73,14 @@ __device__ __forceinline__ float to_float(bf16_t v) { return __uint_as_float((ui
 // Round-to-nearest-even conversions from FP32.
 template <typename T> __device__ __forceinline__ T from_float(float v);
 template <> __device__ __forceinline__ float from_float<float>(float v) { return v; }
-template <> __device__ __forceinline__ __half from_float<__half>(float v) { return __float2half_rn(v); }
+// The value is pinned in an FP32 register first: otherwise the compiler may
+// fuse the multiply that produced it into an FMA with FP16 output (one
+// rounding instead of FP32-then-FP16), and results would depend on the
+// kernel configuration.
+template <> __device__ __forceinline__ __half from_float<__half>(float v) {
+    asm volatile("" : "+v"(v));
+    return __float2half_rn(v);
+}
 template <> __device__ __forceinline__ bf16_t from_float<bf16_t>(float v) {
     uint32_t u = __float_as_uint(v);
     bf16_t r;
