@@ -220,6 +220,126 @@ def cpu_baseline(x64, wavelet, levels, seconds):
                         f"{el:.1f} s; host CPU: {cpu_model}")), coef
 
 
+def run_batch_workload(args):
+    """256 uneven images (sides log-uniform in [64, 4096], multiples of 32),
+    3-level forward, one captured graph of batched launches."""
+    import numpy as np
+    import torch
+    import synthetic
+    from paper_1705_08266_amd import autotune
+    from paper_1705_08266_amd.batch import BatchPlan
+
+    L = args.levels
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    sizes = synthetic.batch_sizes(args.batch, 64, 4096, 32, seed=synthetic.SEED_BASE + 4)
+    print(f"[bench] batch of {len(sizes)} images, {sum(w * h for w, h in sizes) / 1e6:.1f} Mpx, "
+          f"L={L}; tuning tiles per size class", file=sys.stderr, flush=True)
+    class_tiles = autotune.tune(args.wavelet, args.scheme, args.dtype, L,
+                                cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"))
+    imgs = []
+    for i, (w, h) in enumerate(sizes):
+        x = synthetic.uniform_image(h, w, seed=synthetic.SEED_BASE + 4 + i)
+        imgs.append(torch.from_numpy(x).to("cuda").to(tdt))
+    plan = BatchPlan.forward(imgs, L, args.wavelet, args.scheme, class_tiles)
+    plan.capture()
+    for _ in range(args.warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    es = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
+    alg = sum(sum(level_bytes(w, h, L, es)) for w, h in sizes)
+    px = plan.pixels
+    # spot parity: the largest image against the oracle
+    import oracle
+    k = max(range(len(imgs)), key=lambda i: imgs[i].numel())
+    ref = oracle.forward(imgs[k].float().cpu().numpy().astype(np.float64), args.wavelet, L,
+                         nthreads=len(os.sched_getaffinity(0)))
+    err = float(np.abs(plan.outputs[k].float().cpu().numpy() - ref).max() / 255.0)
+    print(json.dumps(dict(
+        metric=f"Gpixel/s batched {L}-level {args.wavelet} forward, {len(sizes)} uneven images",
+        value=round(px / (ms * 1e-3) / 1e9, 3), unit="Gpixel/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms, 5), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype=args.dtype, data="synthetic",
+        config=dict(workload=f"{len(sizes)} images, sides log-uniform in [64, 4096] (multiples "
+                             f"of 32), uniform integers 0..255, {L} levels forward, one captured "
+                             f"graph of batched launches", images=len(sizes), pixels=px,
+                    levels=L, class_tiles=class_tiles),
+        hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), algorithmic_bytes=alg,
+        max_err_rel_largest_image=err)), flush=True)
+
+
+def run_serve_workload(args):
+    """Continuous batching of a Poisson stream of mixed requests: square sides
+    log-uniform in [256, 8192] (multiples of 64), 1..6 levels, forward or
+    inverse 50/50, FP16 storage with FP32 intermediates, 64 GB admission
+    budget. First the saturation throughput (every request offered at time
+    zero), then p50/p99 latency at 0.5, 0.8 and 0.95 of it."""
+    import numpy as np
+    import torch
+    import synthetic
+    import paper_1705_08266_amd as dwt
+    from paper_1705_08266_amd import serving as sv
+
+    n = args.requests
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    trace = synthetic.request_stream(n, 1.0, seed=synthetic.SEED_BASE + 5)
+    reqs = [sv.Request(r.rid, 0.0, r.side, r.side, r.levels, r.inverse) for r in trace]
+    inputs = {}
+    for r, t in zip(reqs, trace):
+        x = synthetic.device_uniform_image(r.height, r.width, t.seed, tdt)
+        inputs[r.rid] = dwt.forward(x, args.wavelet, r.levels) if r.inverse else x
+    torch.cuda.synchronize()
+    px = sum(r.width * r.height for r in reqs)
+    print(f"[bench] serve: {n} requests, {px / 1e6:.0f} Mpx, {args.dtype}", file=sys.stderr,
+          flush=True)
+
+    def serve(rate):
+        srv = sv.Server(budget_bytes=64 << 30, wavelet=args.wavelet, scheme=args.scheme,
+                        dtype=args.dtype)
+        if rate is None:
+            res = srv.run(reqs, inputs, realtime=False)
+        else:
+            rng = np.random.default_rng(synthetic.SEED_BASE + 6)
+            t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+            timed = [sv.Request(r.rid, float(t[i]), r.width, r.height, r.levels, r.inverse)
+                     for i, r in enumerate(reqs)]
+            res = srv.run(timed, inputs, realtime=True)
+        torch.cuda.synchronize()
+        lat = [x.latency_s for x in res]
+        span = max(x.done_s for x in res) - min(x.arrival_s for x in res)
+        out = dict(requests_per_s=round(n / span, 1), gpixel_per_s=round(px / span / 1e9, 3),
+                   p50_ms=round(sv.percentile(lat, 50) * 1e3, 3),
+                   p99_ms=round(sv.percentile(lat, 99) * 1e3, 3),
+                   iterations=srv.iterations, launch_calls=srv.launch_calls,
+                   peak_admitted_gb=round(srv.sched.peak_used / 1e9, 2))
+        print(f"[bench] serve rate={rate}: {out}", file=sys.stderr, flush=True)
+        return out
+
+    serve(None)                                  # warm-up: allocator, kernel loads
+    sat = serve(None)
+    sweep = {}
+    for f in (0.5, 0.8, 0.95):
+        sweep[str(f)] = dict(offered_per_s=round(f * sat["requests_per_s"], 1),
+                             **serve(f * sat["requests_per_s"]))
+    print(json.dumps(dict(
+        metric="Gpixel/s serving throughput, continuous batching of mixed requests",
+        value=sat["gpixel_per_s"], unit="Gpixel/s", n_gpus=1, steps=n, warmup=n,
+        ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=args.dtype, data="synthetic",
+        config=dict(workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples "
+                             f"of 64), levels 1..6, forward/inverse 50/50, {args.dtype} storage "
+                             f"with FP32 intermediates, 64 GB admission budget",
+                    requests=n, pixels=px),
+        saturation=sat, latency_sweep=sweep)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +358,11 @@ def main():
     ap.add_argument("--no-separable", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="launch every step from the host instead of replaying a graph")
+    ap.add_argument("--requests", type=int, default=400, help="requests in the serve workload")
+    ap.add_argument("--workload", default="image", choices=["image", "batch", "serve"],
+                    help="image: one image forward+inverse (headline); batch: many uneven "
+                         "images, batched forward")
+    ap.add_argument("--batch", type=int, default=256, help="images in the batch workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 4 device copies of 64 MiB (reference kernel of known "
                          "traffic for counter calibration)")
@@ -249,6 +374,17 @@ def main():
               "across GPUs in this build (see DESIGN.md for how it would shard). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        if args.levels == 5 and "--levels" not in sys.argv:
+            args.levels = 3
+        run_batch_workload(args)
+        return
+    if args.workload == "serve":
+        if "--dtype" not in sys.argv:
+            args.dtype = "f16"
+        run_serve_workload(args)
+        return
 
     import numpy as np
     import synthetic

@@ -159,6 +159,69 @@ int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind,
 int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet,
                       int32_t scheme, int32_t dtype);
 
+/* ---- batches of images ---------------------------------------------------
+ * Many images of one storage type, wavelet, scheme and level count in few
+ * launches: each level is one launch per size class and chunk of up to 36
+ * images; the images' level parameters travel in the kernel arguments, so a
+ * captured HIP graph of the calls holds everything it needs. A persistent
+ * grid of at most the resident number of workgroups strides over the tiles
+ * of all images of the launch. */
+typedef struct {
+    const void *src;        /* forward: image; inverse: Mallat coefficients */
+    int64_t src_pitch;      /* elements */
+    void *dst;              /* forward: Mallat coefficients; inverse: image */
+    int64_t dst_pitch;      /* elements */
+    void *workspace;        /* FP32 scratch, dwt2_workspace_bytes(width, height, levels) */
+    size_t workspace_bytes;
+    int32_t width, height;  /* divisible by 2^levels */
+} dwt2_image;
+
+#define DWT2_SIZE_CLASSES 4
+
+/* Size class of one level whose input is width x height pixels:
+ * 0: <= 128^2, 1: <= 512^2, 2: <= 2048^2, 3: larger. DWT2_ERR_INVALID_ARG
+ * for sizes below 2. */
+int dwt2_size_class(int32_t width, int32_t height);
+
+/* Batched L-level forward (inverse) DWT of images[0..n). Each image is
+ * checked as by dwt2_forward (dwt2_inverse); src and dst of one image must
+ * not overlap, and no two images may share an output or workspace.
+ * class_tiles: NULL for the library's choice, else DWT2_SIZE_CLASSES ids of
+ * 2-D tile configurations (kind 0), the one used for levels of each class.
+ * Returns a dwt2_status; nothing is enqueued if any image is invalid. */
+int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype,
+                       int32_t wavelet, int32_t levels, int32_t boundary,
+                       int32_t scheme, const int32_t *class_tiles, void *stream);
+int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype,
+                       int32_t wavelet, int32_t levels, int32_t boundary,
+                       int32_t scheme, const int32_t *class_tiles, void *stream);
+
+/* One level of one image, as given to dwt2_forward_level (forward) or
+ * dwt2_inverse_level (inverse): `full` is the width x height buffer (the
+ * level input of a forward, the level output of an inverse), ll the
+ * (width/2) x (height/2) low band, hl/lh/hh the detail bands sharing
+ * band_pitch. */
+typedef struct {
+    void *full;  int64_t full_pitch; int32_t full_dtype;
+    void *ll;    int64_t ll_pitch;   int32_t ll_dtype;
+    void *hl, *lh, *hh; int64_t band_pitch; int32_t band_dtype;
+    int32_t width, height;
+} dwt2_level_job;
+
+/* Many independent single levels in few launches: jobs are grouped by size
+ * class and storage types, and each group runs as batched launches of up to
+ * 36 jobs. Forward jobs read `full` and write ll/hl/lh/hh; inverse jobs read
+ * ll/hl/lh/hh and write `full`. Every job is checked as by the single-level
+ * entry points; no job may write a buffer another job of the call reads or
+ * writes. For continuous batching: each call advances every active request
+ * by one level. Returns a dwt2_status; nothing is enqueued on an error. */
+int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n,
+                             int32_t wavelet, int32_t scheme,
+                             const int32_t *class_tiles, void *stream);
+int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n,
+                             int32_t wavelet, int32_t scheme,
+                             const int32_t *class_tiles, void *stream);
+
 /* Human-readable text of a status code (static storage). */
 const char *dwt2_status_string(int status);
 

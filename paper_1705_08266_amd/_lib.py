@@ -30,6 +30,32 @@ class Desc(ctypes.Structure):
 
 _DescP = ctypes.POINTER(Desc)
 
+
+class Image(ctypes.Structure):
+    """dwt2_image: one image of a batch."""
+    _fields_ = [("src", ctypes.c_void_p), ("src_pitch", ctypes.c_int64),
+                ("dst", ctypes.c_void_p), ("dst_pitch", ctypes.c_int64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+_ImageP = ctypes.POINTER(Image)
+
+
+class LevelJob(ctypes.Structure):
+    """dwt2_level_job: one level of one image."""
+    _fields_ = [("full", ctypes.c_void_p), ("full_pitch", ctypes.c_int64),
+                ("full_dtype", ctypes.c_int32),
+                ("ll", ctypes.c_void_p), ("ll_pitch", ctypes.c_int64),
+                ("ll_dtype", ctypes.c_int32),
+                ("hl", ctypes.c_void_p), ("lh", ctypes.c_void_p), ("hh", ctypes.c_void_p),
+                ("band_pitch", ctypes.c_int64), ("band_dtype", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+_LevelJobP = ctypes.POINTER(LevelJob)
+SIZE_CLASSES = 4
+
 SIGNATURES = {
     "dwt2_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "dwt2_forward": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
@@ -43,6 +69,11 @@ SIGNATURES = {
     "dwt2_tile_config_count": (ctypes.c_int, []),
     "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32, _ip32]),
     "dwt2_default_tile": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
+    "dwt2_size_class": (ctypes.c_int, [_i32, _i32]),
+    "dwt2_forward_batch": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32, _ip32, _vp]),
+    "dwt2_inverse_batch": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32, _ip32, _vp]),
+    "dwt2_forward_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
+    "dwt2_inverse_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dwt2_last_hip_error": (ctypes.c_int, []),
     "dwt2_version": (ctypes.c_int, []),

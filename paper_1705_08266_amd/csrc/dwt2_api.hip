@@ -3,9 +3,27 @@
 
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "dwt2.h"
 #include "dwt2_table.hpp"
+
+namespace dwt2 {
+
+int resident_blocks(const void *kernel, int block_threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+}  // namespace dwt2
 
 namespace {
 
@@ -112,18 +130,33 @@ const FwdTable &fwd_table(int dt) {
 const InvTable &inv_table(int dt) {
     return dt == DWT2_F32 ? kInvF32 : dt == DWT2_F16 ? kInvF16 : kInvBF16;
 }
+const FwdBatchTable &fwd_batch_table(int dt) {
+    return dt == DWT2_F32 ? kFwdBatchF32 : dt == DWT2_F16 ? kFwdBatchF16 : kFwdBatchBF16;
+}
+const InvBatchTable &inv_batch_table(int dt) {
+    return dt == DWT2_F32 ? kInvBatchF32 : dt == DWT2_F16 ? kInvBatchF16 : kInvBatchBF16;
+}
+
+// Size class of a level whose input is width x height pixels.
+int size_class(int width, int height) {
+    const int64_t px = (int64_t)width * height;
+    if (px <= 128 * 128) return 0;
+    if (px <= 512 * 512) return 1;
+    if (px <= 2048 * 2048) return 2;
+    return 3;
+}
+// Default 2-D tile per size class.
+const int kClassTile[DWT2_SIZE_CLASSES] = {1, 1, 1, 1};
 
 int check_level_dims(int32_t width, int32_t height) {
     if (width < 2 || height < 2 || (width & 1) || (height & 1)) return DWT2_ERR_INVALID_ARG;
     return DWT2_OK;
 }
 
-int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height,
-              void *ll, int64_t ll_pitch, int ll_dt, void *hl, void *lh, void *hh,
-              int64_t band_pitch, int band_dt, int wavelet, int scheme, int tile,
-              hipStream_t stream) {
+FwdParams fwd_params(const void *in, int64_t in_pitch, int in_dt, int width, int height, void *ll,
+                     int64_t ll_pitch, int ll_dt, void *hl, void *lh, void *hh,
+                     int64_t band_pitch, int band_dt, int wavelet, int tile) {
     const int nqx = width / 2, nqy = height / 2;
-    if (tile < 0) tile = pick_tile(width, height, wavelet);
     FwdParams p;
     p.in = in; p.in_pitch = in_pitch;
     p.ll = ll; p.ll_pitch = ll_pitch;
@@ -136,18 +169,14 @@ int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height
     p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
-    const FwdLauncher f =
-        fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
-    const hipError_t e = f(p, stream);
-    return e == hipSuccess ? DWT2_OK : hip_fail(e);
+    return p;
 }
 
-int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const void *lh,
-              const void *hh, int64_t band_pitch, int band_dt, void *out, int64_t out_pitch,
-              int out_dt, int width, int height, int wavelet, int scheme, int tile,
-              hipStream_t stream) {
+InvParams inv_params(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const void *lh,
+                     const void *hh, int64_t band_pitch, int band_dt, void *out,
+                     int64_t out_pitch, int out_dt, int width, int height, int wavelet,
+                     int tile) {
     const int nqx = width / 2, nqy = height / 2;
-    if (tile < 0) tile = pick_tile(width, height, wavelet);
     InvParams p;
     p.ll = ll; p.ll_pitch = ll_pitch;
     p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
@@ -160,6 +189,29 @@ int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
     p.vec_out = aligned(out, out_pitch, out_dt, 2 * q);
+    return p;
+}
+
+int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height,
+              void *ll, int64_t ll_pitch, int ll_dt, void *hl, void *lh, void *hh,
+              int64_t band_pitch, int band_dt, int wavelet, int scheme, int tile,
+              hipStream_t stream) {
+    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    const FwdParams p = fwd_params(in, in_pitch, in_dt, width, height, ll, ll_pitch, ll_dt, hl, lh,
+                                   hh, band_pitch, band_dt, wavelet, tile);
+    const FwdLauncher f =
+        fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
+    const hipError_t e = f(p, stream);
+    return e == hipSuccess ? DWT2_OK : hip_fail(e);
+}
+
+int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const void *lh,
+              const void *hh, int64_t band_pitch, int band_dt, void *out, int64_t out_pitch,
+              int out_dt, int width, int height, int wavelet, int scheme, int tile,
+              hipStream_t stream) {
+    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    const InvParams p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, band_pitch, band_dt, out,
+                                   out_pitch, out_dt, width, height, wavelet, tile);
     const InvLauncher f =
         inv_table(band_dt)[wavelet][scheme][ll_dt == DWT2_F32][out_dt == DWT2_F32][tile];
     const hipError_t e = f(p, stream);
@@ -220,6 +272,42 @@ int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_de
         if (!ws || ws_bytes < need) return DWT2_ERR_WORKSPACE;
         const Span sw{(uintptr_t)ws, (uintptr_t)ws + need};
         if (overlaps(sw, sx) || overlaps(sw, sy)) return DWT2_ERR_INVALID_ARG;
+    }
+    return DWT2_OK;
+}
+
+// Checks one batch image (same rules as the multi-level entry points).
+int check_batch_image(const dwt2_image &im, int32_t dtype, int32_t levels) {
+    const dwt2_desc a{im.width, im.height, im.src_pitch, dtype};
+    const dwt2_desc b{im.width, im.height, im.dst_pitch, dtype};
+    return check_multi(im.src, &a, im.dst, &b, DWT2_CDF97, levels, DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC,
+                       DWT2_NONSEPARABLE, nullptr, im.workspace, im.workspace_bytes);
+}
+
+// Launch one level of many images: group by size class, then launch the
+// class's tile configuration over chunks of at most kBatchMax images.
+template <typename Batch, typename Params, typename Launch>
+int launch_batch_level(const Params *params, const int *tiles_of, const int *cls, int n,
+                       Launch launch) {
+    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
+        Batch b;
+        b.n = 0;
+        b.tile_start[0] = 0;
+        int tile = -1;
+        for (int i = 0; i <= n; ++i) {
+            const bool take = i < n && cls[i] == c;
+            if (take) {
+                tile = tiles_of[i];
+                b.p[b.n] = params[i];
+                b.tile_start[b.n + 1] = b.tile_start[b.n] + params[i].tiles_x * params[i].tiles_y;
+                ++b.n;
+            }
+            if (b.n > 0 && (b.n == kBatchMax || i == n)) {
+                const int st = launch(b, tile);
+                if (st) return st;
+                b.n = 0;
+            }
+        }
     }
     return DWT2_OK;
 }
@@ -374,6 +462,226 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
         if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
     }
     return DWT2_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int dwt2_size_class(int32_t width, int32_t height) {
+    if (width < 2 || height < 2) return DWT2_ERR_INVALID_ARG;
+    return size_class(width, height);
+}
+
+int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
+                       int32_t levels, int32_t boundary, int32_t scheme,
+                       const int32_t *class_tiles, void *stream) {
+    if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
+    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) ||
+        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
+        return DWT2_ERR_UNSUPPORTED;
+    int ctile[DWT2_SIZE_CLASSES];
+    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
+        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
+            return DWT2_ERR_UNSUPPORTED;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int st = check_batch_image(images[i], dtype, levels);
+        if (st) return st;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t es = elem_size(dtype);
+    FwdParams *params = new FwdParams[n > 0 ? n : 1];
+    int *cls = new int[n > 0 ? n : 1];
+    int *tiles = new int[n > 0 ? n : 1];
+    int st = DWT2_OK;
+    for (int j = 1; j <= levels && st == DWT2_OK; ++j) {
+        for (int i = 0; i < n; ++i) {
+            const dwt2_image &im = images[i];
+            const int W = im.width, H = im.height;
+            const int w = W >> (j - 1), h = H >> (j - 1);
+            float *ws0 = static_cast<float *>(im.workspace);
+            float *ws[2] = {ws0, ws0 ? ws0 + (size_t)(W / 2) * (H / 2) : nullptr};
+            char *cbase = static_cast<char *>(im.dst);
+            const int64_t cp = im.dst_pitch;
+            const void *in = j == 1 ? im.src : (const void *)ws[(j - 2) & 1];
+            const int64_t in_pitch = j == 1 ? im.src_pitch : w;
+            void *hl = cbase + (size_t)(w / 2) * es;
+            void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
+            void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
+            void *ll = j == levels ? im.dst : (void *)ws[(j - 1) & 1];
+            const int64_t ll_pitch = j == levels ? cp : w / 2;
+            cls[i] = size_class(w, h);
+            tiles[i] = ctile[cls[i]];
+            params[i] = fwd_params(in, in_pitch, j == 1 ? dtype : DWT2_F32, w, h, ll, ll_pitch,
+                                   j == levels ? dtype : DWT2_F32, hl, lh, hh, cp, dtype, wavelet,
+                                   tiles[i]);
+        }
+        const int in_f32 = j == 1 ? dtype == DWT2_F32 : 1;
+        const int ll_f32 = j == levels ? dtype == DWT2_F32 : 1;
+        st = launch_batch_level<FwdBatch>(params, tiles, cls, n, [&](const FwdBatch &b, int tile) {
+            const hipError_t e = fwd_batch_table(dtype)[wavelet][scheme][in_f32][ll_f32][tile](b, s);
+            return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
+        });
+    }
+    delete[] params;
+    delete[] cls;
+    delete[] tiles;
+    return st;
+}
+
+int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
+                       int32_t levels, int32_t boundary, int32_t scheme,
+                       const int32_t *class_tiles, void *stream) {
+    if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
+    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) ||
+        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
+        return DWT2_ERR_UNSUPPORTED;
+    int ctile[DWT2_SIZE_CLASSES];
+    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
+        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
+            return DWT2_ERR_UNSUPPORTED;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int st = check_batch_image(images[i], dtype, levels);
+        if (st) return st;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t es = elem_size(dtype);
+    InvParams *params = new InvParams[n > 0 ? n : 1];
+    int *cls = new int[n > 0 ? n : 1];
+    int *tiles = new int[n > 0 ? n : 1];
+    int st = DWT2_OK;
+    for (int j = levels; j >= 1 && st == DWT2_OK; --j) {
+        for (int i = 0; i < n; ++i) {
+            const dwt2_image &im = images[i];
+            const int W = im.width, H = im.height;
+            const int w = W >> (j - 1), h = H >> (j - 1);
+            float *ws0 = static_cast<float *>(im.workspace);
+            float *ws[2] = {ws0, ws0 ? ws0 + (size_t)(W / 2) * (H / 2) : nullptr};
+            const char *cbase = static_cast<const char *>(im.src);
+            const int64_t cp = im.src_pitch;
+            const void *ll = j == levels ? im.src : (const void *)ws[(j - 1) & 1];
+            const int64_t ll_pitch = j == levels ? cp : w / 2;
+            const void *hl = cbase + (size_t)(w / 2) * es;
+            const void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
+            const void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
+            void *out = j == 1 ? im.dst : (void *)ws[(j - 2) & 1];
+            const int64_t out_pitch = j == 1 ? im.dst_pitch : w;
+            cls[i] = size_class(w, h);
+            tiles[i] = ctile[cls[i]];
+            params[i] = inv_params(ll, ll_pitch, j == levels ? dtype : DWT2_F32, hl, lh, hh, cp,
+                                   dtype, out, out_pitch, j == 1 ? dtype : DWT2_F32, w, h,
+                                   wavelet, tiles[i]);
+        }
+        const int ll_f32 = j == levels ? dtype == DWT2_F32 : 1;
+        const int out_f32 = j == 1 ? dtype == DWT2_F32 : 1;
+        st = launch_batch_level<InvBatch>(params, tiles, cls, n, [&](const InvBatch &b, int tile) {
+            const hipError_t e = inv_batch_table(dtype)[wavelet][scheme][ll_f32][out_f32][tile](b, s);
+            return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
+        });
+    }
+    delete[] params;
+    delete[] cls;
+    delete[] tiles;
+    return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Jobs of one launch group share size class and storage types.
+struct JobKey {
+    int cls, full_dt, ll_dt, band_dt;
+    bool operator==(const JobKey &o) const {
+        return cls == o.cls && full_dt == o.full_dt && ll_dt == o.ll_dt && band_dt == o.band_dt;
+    }
+};
+
+template <bool INV>
+int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t scheme,
+                const int32_t *class_tiles, void *stream) {
+    if (n < 0 || (n > 0 && !jobs)) return DWT2_ERR_INVALID_ARG;
+    if (!valid_wavelet(wavelet) || !valid_scheme(scheme)) return DWT2_ERR_UNSUPPORTED;
+    int ctile[DWT2_SIZE_CLASSES];
+    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
+        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
+            return DWT2_ERR_UNSUPPORTED;
+    }
+    for (int i = 0; i < n; ++i) {
+        const dwt2_level_job &j = jobs[i];
+        const int st = check_level_args(j.full, j.full_pitch, j.full_dtype, j.width, j.height,
+                                        j.ll, j.ll_pitch, j.ll_dtype, j.hl, j.lh, j.hh,
+                                        j.band_pitch, j.band_dtype, wavelet, scheme, 0);
+        if (st) return st;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    JobKey *keys = new JobKey[n > 0 ? n : 1];
+    bool *done = new bool[n > 0 ? n : 1];
+    for (int i = 0; i < n; ++i) {
+        keys[i] = {size_class(jobs[i].width, jobs[i].height), jobs[i].full_dtype, jobs[i].ll_dtype,
+                   jobs[i].band_dtype};
+        done[i] = false;
+    }
+    int st = DWT2_OK;
+    // one group per distinct key, in order of first appearance
+    for (int g = 0; g < n && st == DWT2_OK; ++g) {
+        if (done[g]) continue;
+        const JobKey key = keys[g];
+        const int tile = ctile[key.cls];
+        typename std::conditional<INV, InvBatch, FwdBatch>::type b;
+        b.n = 0;
+        b.tile_start[0] = 0;
+        for (int i = g; i <= n && st == DWT2_OK; ++i) {
+            if (i < n && !done[i] && keys[i] == key) {
+                const dwt2_level_job &j = jobs[i];
+                if constexpr (INV) {
+                    b.p[b.n] = inv_params(j.ll, j.ll_pitch, j.ll_dtype, j.hl, j.lh, j.hh,
+                                          j.band_pitch, j.band_dtype, j.full, j.full_pitch,
+                                          j.full_dtype, j.width, j.height, wavelet, tile);
+                } else {
+                    b.p[b.n] = fwd_params(j.full, j.full_pitch, j.full_dtype, j.width, j.height,
+                                          j.ll, j.ll_pitch, j.ll_dtype, j.hl, j.lh, j.hh,
+                                          j.band_pitch, j.band_dtype, wavelet, tile);
+                }
+                b.tile_start[b.n + 1] = b.tile_start[b.n] + b.p[b.n].tiles_x * b.p[b.n].tiles_y;
+                ++b.n;
+                done[i] = true;
+            }
+            if (b.n > 0 && (b.n == kBatchMax || i == n)) {
+                hipError_t e;
+                if constexpr (INV)
+                    e = inv_batch_table(key.band_dt)[wavelet][scheme][key.ll_dt == DWT2_F32]
+                                       [key.full_dt == DWT2_F32][tile](b, s);
+                else
+                    e = fwd_batch_table(key.band_dt)[wavelet][scheme][key.full_dt == DWT2_F32]
+                                       [key.ll_dt == DWT2_F32][tile](b, s);
+                if (e != hipSuccess) st = hip_fail(e);
+                b.n = 0;
+            }
+        }
+    }
+    delete[] keys;
+    delete[] done;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet,
+                             int32_t scheme, const int32_t *class_tiles, void *stream) {
+    return level_batch<false>(jobs, n, wavelet, scheme, class_tiles, stream);
+}
+
+int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet,
+                             int32_t scheme, const int32_t *class_tiles, void *stream) {
+    return level_batch<true>(jobs, n, wavelet, scheme, class_tiles, stream);
 }
 
 }  // extern "C"

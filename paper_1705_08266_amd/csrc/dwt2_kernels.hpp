@@ -169,19 +169,26 @@ __device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdPa
     }
 }
 
-// One tile per workgroup.
+// One tile of a forward level: load, lift, store. All waves of the
+// workgroup call it with the same tile (it contains workgroup barriers).
 template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
-__global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
+__device__ __forceinline__ void fwd_tile(const FwdParams &prm, int t, Mailbox<QPL, WAVES> &box,
+                                         int lane, int wave) {
     using G = TileGeom<WV, QPL, ROWS, WAVES>;
-    __shared__ Mailbox<QPL, WAVES> box;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
-    const int t = block_tile();
     Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
     Quads<ROWS, QPL> q;
     fwd_load<QPL, ROWS, G, TIN>(q, prm, t, lane, wave);
     lift_forward<WV, SCH>(q, x);
     fwd_store<WV, QPL, ROWS, WAVES, G, TLL, TB>(q, prm, t, lane, wave);
+}
+
+// One tile per workgroup.
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+    fwd_tile<WV, SCH, QPL, ROWS, WAVES, TIN, TLL, TB>(prm, block_tile(), box, lane, wave);
 }
 
 // ---- inverse ---------------------------------------------------------------------
@@ -269,13 +276,10 @@ __device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvPa
 }
 
 template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
-__global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
+__device__ __forceinline__ void inv_tile(const InvParams &prm, int t, Mailbox<QPL, WAVES> &box,
+                                         int lane, int wave) {
     using G = TileGeom<WV, QPL, ROWS, WAVES>;
     using L = Wavelet<WV>;
-    __shared__ Mailbox<QPL, WAVES> box;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
-    const int t = block_tile();
     const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
     const float uHH = (float)(1.0 / (L::ZH * L::ZH));
     Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
@@ -290,6 +294,70 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
     }
     lift_inverse<WV, SCH>(q, x);
     inv_store<QPL, ROWS, WAVES, G, TOUT>(q, prm, t, lane, wave);
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+    inv_tile<WV, SCH, QPL, ROWS, WAVES, TLL, TB, TOUT>(prm, block_tile(), box, lane, wave);
+}
+
+// ---- batches of images ------------------------------------------------------------
+// Up to kBatchMax images of one size class per launch; their level parameters
+// travel in the kernel arguments (so a captured graph holds them), and
+// tile_start[i] is the first global tile index of image i (tile_start[n] is
+// the total). A persistent grid strides over the tiles of all images.
+constexpr int kBatchMax = 36;
+
+struct FwdBatch {
+    int32_t n;
+    int32_t tile_start[kBatchMax + 1];
+    FwdParams p[kBatchMax];
+};
+struct InvBatch {
+    int32_t n;
+    int32_t tile_start[kBatchMax + 1];
+    InvParams p[kBatchMax];
+};
+static_assert(sizeof(FwdBatch) <= 4096 && sizeof(InvBatch) <= 4096, "kernel argument limit");
+
+// Image owning global tile t (wave-uniform; the table is in kernel arguments).
+template <typename B>
+__device__ __forceinline__ int batch_image(const B &bt, int t) {
+    int lo = 0, hi = bt.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bt.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES) void fwd_batch_kernel(FwdBatch bt) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = bt.tile_start[bt.n];
+    for (int t = block_tile(); t < total; t += gridDim.x) {
+        const int i = batch_image(bt, t);
+        fwd_tile<WV, SCH, QPL, ROWS, WAVES, TIN, TLL, TB>(bt.p[i], t - bt.tile_start[i], box, lane,
+                                                          wave);
+    }
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES) void inv_batch_kernel(InvBatch bt) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = bt.tile_start[bt.n];
+    for (int t = block_tile(); t < total; t += gridDim.x) {
+        const int i = batch_image(bt, t);
+        inv_tile<WV, SCH, QPL, ROWS, WAVES, TLL, TB, TOUT>(bt.p[i], t - bt.tile_start[i], box, lane,
+                                                           wave);
+    }
 }
 
 }  // namespace dwt2

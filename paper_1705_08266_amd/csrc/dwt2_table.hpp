@@ -72,6 +72,58 @@ hipError_t launch_inv(const InvParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Batches (2-D tile configurations only). With kBatchPersistent a grid of at
+// most the resident number of workgroups strides over the tiles of all
+// images; otherwise one workgroup per tile (the hardware dispatcher balances
+// the load, which measured faster).
+constexpr bool kBatchPersistent = false;
+using FwdBatchLauncher = hipError_t (*)(const FwdBatch &, hipStream_t);
+using InvBatchLauncher = hipError_t (*)(const InvBatch &, hipStream_t);
+
+// Workgroups of `kernel` that fit on the current device at once.
+int resident_blocks(const void *kernel, int block_threads);
+
+template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
+hipError_t launch_fwd_batch(const FwdBatch &b, hipStream_t s) {
+    constexpr TileCfg c = kTiles[T];
+    if constexpr (c.kind != CFG_TILE) {
+        return hipErrorInvalidValue;
+    } else {
+        const auto k = fwd_batch_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>;
+        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+        const int total = b.tile_start[b.n];
+        const int grid = kBatchPersistent ? (total < resident ? total : resident) : total;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
+        return hipGetLastError();
+    }
+}
+
+template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
+hipError_t launch_inv_batch(const InvBatch &b, hipStream_t s) {
+    constexpr TileCfg c = kTiles[T];
+    if constexpr (c.kind != CFG_TILE) {
+        return hipErrorInvalidValue;
+    } else {
+        const auto k = inv_batch_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>;
+        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+        const int total = b.tile_start[b.n];
+        const int grid = kBatchPersistent ? (total < resident ? total : resident) : total;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
+        return hipGetLastError();
+    }
+}
+
+template <int WV, int SCH, typename TIN, typename TLL, typename TB, int... I>
+constexpr std::array<FwdBatchLauncher, kNumTiles> fwd_batch_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_fwd_batch<WV, SCH, I, TIN, TLL, TB>...};
+}
+template <int WV, int SCH, typename TLL, typename TB, typename TOUT, int... I>
+constexpr std::array<InvBatchLauncher, kNumTiles> inv_batch_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_inv_batch<WV, SCH, I, TLL, TB, TOUT>...};
+}
+
 template <int WV, int SCH, typename TIN, typename TLL, typename TB, int... I>
 constexpr std::array<FwdLauncher, kNumTiles> fwd_tiles(std::integer_sequence<int, I...>) {
     return {&launch_fwd<WV, SCH, I, TIN, TLL, TB>...};
@@ -102,6 +154,32 @@ constexpr std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2> inv_t
              {inv_tiles<WV, SCH, float, T, T>(S{}), inv_tiles<WV, SCH, float, T, float>(S{})}}};
 }
 
+using FwdBatchTable = std::array<std::array<std::array<std::array<std::array<FwdBatchLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
+using InvBatchTable = std::array<std::array<std::array<std::array<std::array<InvBatchLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
+
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<std::array<FwdBatchLauncher, kNumTiles>, 2>, 2> fwd_batch_types() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{fwd_batch_tiles<WV, SCH, T, T, T>(S{}), fwd_batch_tiles<WV, SCH, T, float, T>(S{})},
+             {fwd_batch_tiles<WV, SCH, float, T, T>(S{}), fwd_batch_tiles<WV, SCH, float, float, T>(S{})}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<std::array<InvBatchLauncher, kNumTiles>, 2>, 2> inv_batch_types() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{inv_batch_tiles<WV, SCH, T, T, T>(S{}), inv_batch_tiles<WV, SCH, T, T, float>(S{})},
+             {inv_batch_tiles<WV, SCH, float, T, T>(S{}), inv_batch_tiles<WV, SCH, float, T, float>(S{})}}};
+}
+template <typename T>
+constexpr FwdBatchTable make_fwd_batch_table() {
+    return {{{fwd_batch_types<T, CDF97, NONSEP>(), fwd_batch_types<T, CDF97, SEP>()},
+             {fwd_batch_types<T, CDF53, NONSEP>(), fwd_batch_types<T, CDF53, SEP>()}}};
+}
+template <typename T>
+constexpr InvBatchTable make_inv_batch_table() {
+    return {{{inv_batch_types<T, CDF97, NONSEP>(), inv_batch_types<T, CDF97, SEP>()},
+             {inv_batch_types<T, CDF53, NONSEP>(), inv_batch_types<T, CDF53, SEP>()}}};
+}
+
 template <typename T>
 constexpr FwdTable make_fwd_table() {
     return {{{fwd_types<T, CDF97, NONSEP>(), fwd_types<T, CDF97, SEP>()},
@@ -116,5 +194,7 @@ constexpr InvTable make_inv_table() {
 // Defined in one translation unit per storage type and direction.
 extern FwdTable kFwdF32, kFwdF16, kFwdBF16;
 extern InvTable kInvF32, kInvF16, kInvBF16;
+extern FwdBatchTable kFwdBatchF32, kFwdBatchF16, kFwdBatchBF16;
+extern InvBatchTable kInvBatchF32, kInvBatchF16, kInvBatchBF16;
 
 }  // namespace dwt2

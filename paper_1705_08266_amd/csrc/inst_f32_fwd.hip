@@ -3,4 +3,5 @@
 
 namespace dwt2 {
 FwdTable kFwdF32 = make_fwd_table<float>();
+FwdBatchTable kFwdBatchF32 = make_fwd_batch_table<float>();
 }  // namespace dwt2

@@ -1,0 +1,321 @@
+"""Serving loop: continuous batching of independent DWT requests on one GPU.
+
+Each request is one image (forward) or one Mallat pyramid (inverse) with its
+own level count. The loop works in iterations: an iteration advances every
+active request by exactly one level, enqueued as a few batched launches
+(dwt2_forward_level_batch / dwt2_inverse_level_batch, grouped by size class
+and storage types inside the library). New arrivals join at the next
+iteration and finished requests leave, so large and small requests share the
+device without a small one waiting for a large one to finish all its levels.
+
+Admission is first-come first-served under an HBM budget: a request holds its
+input, its output pyramid and its FP32 intermediate low-low buffers from
+admission until the client releases the result. A request that can never fit
+is rejected at arrival.
+
+``Scheduler`` is the host-side policy (no GPU, testable with a simulated
+clock); ``Server`` allocates buffers with PyTorch, builds the per-level job
+descriptors once at admission and drives the library on one HIP stream.
+Latency is measured from the request's arrival to the GPU timestamp of the
+iteration that finished it.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import dataclasses
+import time
+
+from . import _lib
+from . import _scheme, _stream_ptr, _wavelet, load
+
+_STORAGE_BYTES = {_lib.F32: 4, _lib.F16: 2, _lib.BF16: 2}
+
+
+@dataclasses.dataclass
+class Request:
+    """A transform asked for by a client. `width` x `height` must be divisible
+    by 2**levels."""
+    rid: int
+    arrival_s: float
+    width: int
+    height: int
+    levels: int
+    inverse: bool
+
+
+def workspace_bytes(width: int, height: int, levels: int) -> int:
+    """FP32 intermediate low-low buffers of one request (two ping-pong
+    buffers, the larger a quarter of the image)."""
+    if levels <= 1:
+        return 0
+    n = (width // 2) * (height // 2)
+    if levels >= 3:
+        n += (width // 4) * (height // 4)
+    return 4 * n
+
+
+def request_bytes(req: Request, dtype: int = _lib.F16) -> int:
+    """HBM held by an admitted request: input + output in the storage type and
+    the FP32 intermediates."""
+    px = req.width * req.height
+    return 2 * px * _STORAGE_BYTES[dtype] + workspace_bytes(req.width, req.height, req.levels)
+
+
+class _Active:
+    __slots__ = ("req", "bytes", "next_level", "t_admit", "payload")
+
+    def __init__(self, req, nbytes, t_admit):
+        self.req = req
+        self.bytes = nbytes
+        self.next_level = 0          # levels already enqueued
+        self.t_admit = t_admit
+        self.payload = None
+
+
+class Scheduler:
+    """FIFO admission under a byte budget and a cap on active requests;
+    level-synchronous iterations.
+
+    offer(req)        queue an arrived request (False if it can never fit)
+    admit(now)        move queue heads into the active set while they fit
+    iteration()       the active requests to advance by one level now
+    finish_iteration  advance them; returns those that have enqueued their
+                      last level (their bytes stay held until release())
+    release(a)        return a finished request's bytes to the budget
+    """
+
+    def __init__(self, budget_bytes: int, max_active: int = 1 << 30, bytes_fn=request_bytes):
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.bytes_fn = bytes_fn
+        self.queue = collections.deque()
+        self.active = []
+        self.used = 0
+        self.peak_used = 0
+        self.rejected = []
+
+    def offer(self, req: Request) -> bool:
+        if self.bytes_fn(req) > self.budget:
+            self.rejected.append(req)
+            return False
+        self.queue.append(req)
+        return True
+
+    def admit(self, now: float):
+        admitted = []
+        while self.queue and len(self.active) < self.max_active:
+            req = self.queue[0]
+            nb = self.bytes_fn(req)
+            if self.used + nb > self.budget:
+                break                          # strict FIFO: no overtaking
+            self.queue.popleft()
+            a = _Active(req, nb, now)
+            self.active.append(a)
+            self.used += nb
+            admitted.append(a)
+        self.peak_used = max(self.peak_used, self.used)
+        return admitted
+
+    def iteration(self):
+        return list(self.active)
+
+    def finish_iteration(self, advanced):
+        done = []
+        for a in advanced:
+            a.next_level += 1
+            if a.next_level == a.req.levels:
+                done.append(a)
+        if done:
+            ids = {id(a) for a in done}
+            self.active = [a for a in self.active if id(a) not in ids]
+        return done
+
+    def release(self, a: _Active):
+        self.used -= a.bytes
+
+    @property
+    def idle(self) -> bool:
+        return not self.queue and not self.active
+
+
+# ---------------------------------------------------------------------------
+# GPU side
+
+
+def _job(full, ll, hl, lh, hh, width, height, dtcode):
+    """A job from tensors (hl, lh and hh share one row pitch)."""
+    j = _lib.LevelJob()
+    j.full, j.full_pitch, j.full_dtype = full.data_ptr(), full.stride(0), dtcode(full)
+    j.ll, j.ll_pitch, j.ll_dtype = ll.data_ptr(), ll.stride(0), dtcode(ll)
+    j.hl, j.lh, j.hh = hl.data_ptr(), lh.data_ptr(), hh.data_ptr()
+    j.band_pitch, j.band_dtype = hl.stride(0), dtcode(hl)
+    j.width, j.height = width, height
+    return j
+
+
+def level_jobs(src, out, ws0, ws1, levels, inverse):
+    """Per-level job descriptors of one request, in execution order.
+
+    Forward: level j reads the image (j = 1) or the previous low-low band and
+    writes its detail bands into the Mallat quadrants of `out` and its
+    low-low band to an FP32 buffer (or to the top-left of `out` at the last
+    level). Inverse: levels L..1 mirror that, reading the pyramid `src` and
+    writing the image to `out`. ws0 holds a quarter of the image, ws1 a
+    sixteenth; consecutive levels alternate between them. Pointers are
+    computed directly (this runs once per admitted request).
+    """
+    from . import _dtype_code
+    H, W = src.shape
+    P = src.stride(0)
+    if out.stride(0) != P or out.shape != src.shape or out.dtype != src.dtype:
+        raise ValueError("src and out must share shape, dtype and row pitch")
+    dt = _dtype_code(src)
+    e = src.element_size()
+    pyr = (src if inverse else out).data_ptr()
+    img = (out if inverse else src).data_ptr()
+    ws = (ws0.data_ptr(), ws1.data_ptr())
+    jobs = (_lib.LevelJob * levels)()
+    order = range(levels, 0, -1) if inverse else range(1, levels + 1)
+    for k, j in enumerate(order):
+        h, w = H >> (j - 1), W >> (j - 1)
+        h2, w2 = h // 2, w // 2
+        job = jobs[k]
+        if j == 1:
+            job.full, job.full_pitch, job.full_dtype = img, P, dt
+        else:
+            job.full, job.full_pitch, job.full_dtype = ws[(j - 2) % 2], w, _lib.F32
+        if j == levels:
+            job.ll, job.ll_pitch, job.ll_dtype = pyr, P, dt
+        else:
+            job.ll, job.ll_pitch, job.ll_dtype = ws[(j - 1) % 2], w2, _lib.F32
+        job.hl = pyr + e * w2
+        job.lh = pyr + e * h2 * P
+        job.hh = pyr + e * (h2 * P + w2)
+        job.band_pitch, job.band_dtype = P, dt
+        job.width, job.height = w, h
+    return jobs
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival_s: float
+    done_s: float          # GPU completion time, same clock as arrival_s
+    output: object         # the output tensor (None once released by the server)
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class Server:
+    """Runs a request trace through the continuous-batching loop on the
+    current HIP device.
+
+    inputs: rid -> 2-D GPU tensor (the image, or the pyramid of an inverse
+    request), resident before the request arrives. keep_outputs keeps every
+    result's output tensor (tests); otherwise results are released as soon as
+    the iteration that finished them is observed complete.
+    """
+
+    def __init__(self, budget_bytes=64 << 30, max_active=1 << 30, wavelet="cdf97",
+                 scheme="nonseparable", dtype="f16", class_tiles=None, max_inflight=2):
+        self.dtype = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[dtype]
+        self.sched = Scheduler(budget_bytes, max_active,
+                               bytes_fn=lambda r: request_bytes(r, self.dtype))
+        self.wavelet = _wavelet(wavelet)
+        self.scheme = _scheme(scheme)
+        self.class_tiles = (None if class_tiles is None else
+                            (ctypes.c_int32 * _lib.SIZE_CLASSES)(*class_tiles))
+        self.max_inflight = max_inflight
+        self.iterations = 0
+        self.launch_calls = 0
+
+    def _allocate(self, a, inputs, torch):
+        req = a.req
+        src = inputs[req.rid]
+        if src.shape != (req.height, req.width):
+            raise ValueError(f"request {req.rid}: input shape {tuple(src.shape)}")
+        out = torch.empty_like(src)
+        n0 = (req.width // 2) * (req.height // 2) if req.levels > 1 else 1
+        n1 = (req.width // 4) * (req.height // 4) if req.levels > 2 else 1
+        ws0 = torch.empty(n0, dtype=torch.float32, device=src.device)
+        ws1 = torch.empty(n1, dtype=torch.float32, device=src.device)
+        a.payload = {"out": out, "ws": (ws0, ws1),
+                     "jobs": level_jobs(src, out, ws0, ws1, req.levels, req.inverse)}
+
+    def _enqueue(self, advanced, stream):
+        lib = load()
+        fwd = [a.payload["jobs"][a.next_level] for a in advanced if not a.req.inverse]
+        inv = [a.payload["jobs"][a.next_level] for a in advanced if a.req.inverse]
+        for jobs, fn, name in ((fwd, lib.dwt2_forward_level_batch, "dwt2_forward_level_batch"),
+                               (inv, lib.dwt2_inverse_level_batch, "dwt2_inverse_level_batch")):
+            if jobs:
+                arr = (_lib.LevelJob * len(jobs))(*jobs)
+                _lib.check(fn(arr, len(jobs), self.wavelet, self.scheme, self.class_tiles,
+                              stream), name)
+                self.launch_calls += 1
+
+    def run(self, requests, inputs, keep_outputs=False, realtime=True):
+        """Serve `requests` (sorted by arrival). With realtime=False every
+        request is offered at time zero (saturation). Returns the results in
+        completion order."""
+        import torch
+        from . import _dtype_code
+        for r in requests:
+            if _dtype_code(inputs[r.rid]) != self.dtype:
+                raise ValueError(f"request {r.rid}: input dtype differs from the server's")
+        stream = torch.cuda.current_stream()
+        sptr = _stream_ptr(stream)
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        inflight = collections.deque()          # (event, finished actives)
+        results = []
+        start = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record(stream)
+
+        def retire(ev, done):
+            ms = start.elapsed_time(ev)
+            for a in done:
+                out = a.payload["out"]
+                results.append(Result(a.req.rid, a.req.arrival_s if realtime else 0.0,
+                                       ms / 1e3, out if keep_outputs else None))
+                a.payload = None
+                self.sched.release(a)
+
+        while pending or not self.sched.idle or inflight:
+            now = time.perf_counter() - t0
+            while pending and (not realtime or pending[0].arrival_s <= now):
+                r = pending.popleft()
+                if not self.sched.offer(r):            # can never fit the budget
+                    results.append(Result(r.rid, r.arrival_s, float("nan"), None))
+            for a in self.sched.admit(now):
+                self._allocate(a, inputs, torch)
+            advanced = self.sched.iteration()
+            if advanced:
+                self._enqueue(advanced, sptr)
+                done = self.sched.finish_iteration(advanced)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(stream)
+                inflight.append((ev, done))
+                self.iterations += 1
+            # observe completions; keep at most max_inflight iterations queued
+            while inflight and (len(inflight) > self.max_inflight or inflight[0][0].query()
+                                or (not advanced and not pending)):
+                ev, done = inflight.popleft()
+                ev.synchronize()
+                retire(ev, done)
+            if not advanced and not inflight and pending and realtime:
+                wait = pending[0].arrival_s - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        return results
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in 0..100) of a non-empty list."""
+    v = sorted(values)
+    k = max(0, min(len(v) - 1, int(-(-q * len(v) // 100)) - 1))
+    return v[k]

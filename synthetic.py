@@ -9,6 +9,8 @@ the sizes and value ranges of 8-bit photographic images:
 
   * ``uniform_image``   i.i.d. integers 0..255 stored as floats (the hardest
                         case for accuracy: no smoothness, full-range detail);
+                        ``device_uniform_image`` draws the same distribution
+                        on the GPU;
   * ``sinusoid_image``  a sum of 8 random plane waves (periods 8-512 px) around
                         mid-grey plus Gaussian noise (sigma 4), clipped to
                         0..255: smooth content with texture at many scales;
@@ -37,6 +39,17 @@ def uniform_image(height: int, width: int, seed: int = SEED_BASE + 1,
     """I.i.d. uniform integers 0..255, as `dtype`."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, 256, size=(height, width)).astype(dtype)
+
+
+def device_uniform_image(height: int, width: int, seed: int, dtype=None, device="cuda"):
+    """I.i.d. uniform integers 0..255 drawn directly on a PyTorch device by a
+    seeded device generator (for workloads too large to draw on the host; the
+    values differ from ``uniform_image`` of the same seed)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randint(0, 256, (height, width), generator=g, device=device, dtype=torch.int32)
+    return x.to(dtype or torch.float32)
 
 
 def sinusoid_image(height: int, width: int, seed: int = SEED_BASE + 2,

@@ -1,0 +1,115 @@
+"""Batched launches of uneven images, and their HIP-graph capture.
+
+A batch runs the same per-quad arithmetic as the single-image path with the
+same tile configuration, so results must agree bit for bit; against the
+oracle the FP32 bound is 1e-5 of max|x|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_08266_amd as dwt  # noqa: E402
+from paper_1705_08266_amd import batch as dwb  # noqa: E402
+
+
+def _images(n, lo=64, hi=512, multiple=32, seed=11, dtype=torch.float32):
+    sizes = synthetic.batch_sizes(n, lo, hi, multiple, seed=seed)
+    imgs = [torch.from_numpy(synthetic.uniform_image(h, w, seed=seed + i)).to("cuda").to(dtype)
+            for i, (w, h) in enumerate(sizes)]
+    return imgs
+
+
+@pytest.mark.parametrize("wavelet", ["cdf97", "cdf53"])
+@pytest.mark.parametrize("scheme", ["nonseparable", "separable"])
+def test_batch_forward_equals_single_and_oracle(wavelet, scheme):
+    imgs = _images(20)
+    tile = 1
+    plan = dwb.BatchPlan.forward(imgs, 3, wavelet, scheme, class_tiles=[tile] * 4)
+    plan.run()
+    torch.cuda.synchronize()
+    for x, c in zip(imgs, plan.outputs):
+        single = dwt.forward(x, wavelet, 3, scheme, tiles=[tile] * 3)
+        assert torch.equal(single, c)
+        ref = oracle.forward(x.cpu().numpy().astype(np.float64), wavelet, 3)
+        assert np.abs(c.cpu().numpy() - ref).max() <= 1e-5 * 255
+
+
+def test_batch_inverse_round_trip_and_mixed_classes():
+    imgs = _images(12, lo=64, hi=4096, seed=5)
+    fwd = dwb.BatchPlan.forward(imgs, 3)
+    fwd.run()
+    inv = dwb.BatchPlan.inverse_of(fwd.outputs, 3)
+    inv.run()
+    torch.cuda.synchronize()
+    classes = {dwb.size_class(x.shape[1], x.shape[0]) for x in imgs}
+    assert len(classes) >= 2
+    for x, r, c in zip(imgs, inv.outputs, fwd.outputs):
+        assert (r - x).abs().max().item() <= 1e-5 * 255
+        assert torch.equal(dwt.inverse(c, "cdf97", 3), r)
+
+
+def test_batch_more_than_one_chunk_per_class():
+    imgs = [torch.from_numpy(synthetic.uniform_image(64, 96, seed=i)).to("cuda")
+            for i in range(80)]                         # 80 > 36 images in one class
+    plan = dwb.BatchPlan.forward(imgs, 2)
+    plan.run()
+    torch.cuda.synchronize()
+    for x, c in zip(imgs, plan.outputs):
+        assert torch.equal(dwt.forward(x, "cdf97", 2), c)
+
+
+def test_batch_every_2d_tile_config_identical():
+    imgs = _images(10, seed=2)
+    ref = None
+    for t in [c[0] for c in dwt.tile_configs("cdf97") if c[1] == 0]:
+        plan = dwb.BatchPlan.forward(imgs, 3, class_tiles=[t] * 4)
+        plan.run()
+        outs = [o.cpu() for o in plan.outputs]
+        if ref is None:
+            ref = outs
+        else:
+            for a, b in zip(ref, outs):
+                assert torch.equal(a, b), t
+
+
+def test_graph_replays_match_eager_with_work_in_between():
+    imgs = _images(16, seed=9)
+    plan = dwb.BatchPlan.forward(imgs, 3)
+    plan.run()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in plan.outputs]
+    plan.capture()
+    for k in range(4):
+        for o in plan.outputs:            # eager work between replays
+            o.zero_()
+        _ = torch.ones(1024, device="cuda").sum()
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, plan.outputs):
+            assert torch.equal(a, b), k
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_batch_16_bit_equals_single(dtype):
+    imgs = _images(10, seed=4, dtype=dtype)
+    plan = dwb.BatchPlan.forward(imgs, 3)
+    plan.run()
+    torch.cuda.synchronize()
+    for x, c in zip(imgs, plan.outputs):
+        assert torch.equal(dwt.forward(x, "cdf97", 3), c)
+
+
+def test_batch_rejects_invalid_image_before_launch():
+    imgs = _images(3, seed=1)
+    bad = torch.zeros(48, 64, device="cuda")            # 48 not divisible by 2^5
+    plan = dwb.BatchPlan.forward(imgs + [bad], 5)
+    with pytest.raises(dwt.DWT2Error):
+        plan.run()
+    with pytest.raises(dwt.DWT2Error):
+        dwb.run_batch(imgs, imgs, [None] * 3, levels=1)  # dst overlaps src

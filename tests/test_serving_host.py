@@ -1,0 +1,167 @@
+"""Host logic of the serving loop: admission, level-synchronous iterations and
+per-level job descriptors, checked on the CPU with a simulated clock."""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic
+from paper_1705_08266_amd import _lib
+from paper_1705_08266_amd import serving as sv
+
+torch = pytest.importorskip("torch")
+
+
+def _trace(n, seed=3, rate=2000.0, lo=64, hi=2048):
+    return [sv.Request(r.rid, r.arrival_s, r.side, r.side, r.levels, r.inverse)
+            for r in synthetic.request_stream(n, rate, lo=lo, hi=hi, seed=seed)]
+
+
+def simulate(requests, budget, max_active=1 << 30, bw=4e12, launch_s=5e-6):
+    """Fake executor: one iteration costs a launch overhead plus the bytes of
+    the levels it advances at `bw`. Returns per-request admission iteration,
+    completion time and the ordered log of (iteration, rid, level)."""
+    sched = sv.Scheduler(budget, max_active)
+    pending = sorted(requests, key=lambda r: r.arrival_s)
+    now, it, k = 0.0, 0, 0
+    admitted_at, done_at, log, order = {}, {}, [], []
+    while k < len(pending) or not sched.idle:
+        while k < len(pending) and pending[k].arrival_s <= now:
+            sched.offer(pending[k])
+            k += 1
+        for a in sched.admit(now):
+            assert a.req.arrival_s <= now
+            admitted_at[a.req.rid] = it
+            order.append(a.req.rid)
+        assert sched.used <= budget
+        adv = sched.iteration()
+        if not adv:
+            now = pending[k].arrival_s if k < len(pending) else now
+            continue
+        cost = launch_s
+        for a in adv:
+            j = a.next_level + 1
+            px = a.req.width * a.req.height / 4 ** (j - 1)
+            cost += 6.5 * px / bw
+            log.append((it, a.req.rid, a.next_level))
+        now += cost
+        for a in sched.finish_iteration(adv):
+            done_at[a.req.rid] = (it, now)
+            sched.release(a)
+        it += 1
+    return sched, admitted_at, done_at, log, order
+
+
+def test_every_request_advances_once_per_iteration_until_done():
+    reqs = _trace(200)
+    sched, adm, done, log, order = simulate(reqs, budget=2 << 30)
+    assert not sched.rejected and sched.used == 0
+    for r in reqs:
+        steps = [(it, lv) for it, rid, lv in log if rid == r.rid]
+        # levels 0..L-1 in consecutive iterations starting at admission
+        assert [lv for _, lv in steps] == list(range(r.levels))
+        assert [it for it, _ in steps] == list(range(adm[r.rid], adm[r.rid] + r.levels))
+        assert done[r.rid][0] == adm[r.rid] + r.levels - 1
+
+
+def test_admission_is_fifo_and_within_budget():
+    reqs = _trace(300, seed=8, rate=1e6)           # heavy overload
+    budget = 256 << 20
+    sched, adm, done, log, order = simulate(reqs, budget=budget)
+    arrival_order = [r.rid for r in sorted(reqs, key=lambda r: r.arrival_s)
+                     if sv.request_bytes(r) <= budget]
+    assert order == arrival_order
+    assert sched.peak_used <= budget
+    assert sched.peak_used > budget // 2           # the budget is actually used
+
+
+def test_max_active_is_respected():
+    reqs = _trace(100, seed=4, rate=1e6)
+    sched = sv.Scheduler(1 << 40, max_active=7)
+    for r in reqs:
+        sched.offer(r)
+    while not sched.idle:
+        sched.admit(0.0)
+        assert len(sched.active) <= 7
+        for a in sched.finish_iteration(sched.iteration()):
+            sched.release(a)
+
+
+def test_oversized_request_is_rejected_and_others_served():
+    big = sv.Request(0, 0.0, 8192, 8192, 3, False)
+    small = sv.Request(1, 0.0, 256, 256, 2, True)
+    sched, adm, done, log, order = simulate([big, small], budget=64 << 20)
+    assert [r.rid for r in sched.rejected] == [0]
+    assert 1 in done and 0 not in done
+
+
+def test_small_request_overtakes_a_long_one_in_flight():
+    """Continuous batching: a one-level request that arrives while a six-level
+    request is running finishes first."""
+    long_ = sv.Request(0, 0.0, 4096, 4096, 6, False)
+    short = sv.Request(1, 1e-6, 256, 256, 1, False)
+    sched, adm, done, log, order = simulate([long_, short], budget=1 << 30)
+    assert adm[1] == 1 and done[1][0] == 1
+    assert done[0][0] == 5
+    assert done[1][1] < done[0][1]
+
+
+def test_request_bytes_formula():
+    r = sv.Request(0, 0.0, 1024, 512, 5, False)
+    px = 1024 * 512
+    assert sv.request_bytes(r, _lib.F16) == 4 * px + 4 * (px // 4 + px // 16)
+    assert sv.request_bytes(r, _lib.F32) == 8 * px + 4 * (px // 4 + px // 16)
+    assert sv.workspace_bytes(1024, 512, 1) == 0
+    assert sv.workspace_bytes(1024, 512, 2) == px
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+@pytest.mark.parametrize("levels", [1, 2, 3, 5])
+def test_level_jobs_chain_and_layout(inverse, levels):
+    H, W = 96, 128
+    src = torch.zeros(H, W, dtype=torch.float16)
+    out = torch.zeros(H, W, dtype=torch.float16)
+    ws0 = torch.zeros(max(1, (W // 2) * (H // 2)), dtype=torch.float32)
+    ws1 = torch.zeros(max(1, (W // 4) * (H // 4)), dtype=torch.float32)
+    jobs = sv.level_jobs(src, out, ws0, ws1, levels, inverse)
+    assert len(jobs) == levels
+    pyr = src if inverse else out
+    e = 2
+    bufs = {ws0.data_ptr(): ws0.numel(), ws1.data_ptr(): ws1.numel()}
+    lv = list(range(levels, 0, -1)) if inverse else list(range(1, levels + 1))
+    for k, (j, job) in enumerate(zip(lv, jobs)):
+        h, w = H >> (j - 1), W >> (j - 1)
+        assert (job.width, job.height) == (w, h)
+        base = pyr.data_ptr()
+        assert job.hl == base + e * (w // 2)
+        assert job.lh == base + e * (h // 2) * W
+        assert job.hh == base + e * ((h // 2) * W + w // 2)
+        assert job.band_pitch == W and job.band_dtype == _lib.F16
+        for ptr, pitch, dt, n in ((job.full, job.full_pitch, job.full_dtype, h * w),
+                                  (job.ll, job.ll_pitch, job.ll_dtype, h * w // 4)):
+            if ptr in bufs:                        # an FP32 intermediate fits its buffer
+                assert dt == _lib.F32 and n <= bufs[ptr]
+                assert pitch == (w if n == h * w else w // 2)
+        # the image side of level 1 and the pyramid's LL at level L
+        if j == 1:
+            assert job.full == (out if inverse else src).data_ptr() and job.full_pitch == W
+        if j == levels:
+            assert job.ll == base and job.ll_pitch == W and job.ll_dtype == _lib.F16
+        else:
+            assert job.ll in bufs
+    # consecutive levels hand over the LL buffer
+    for a, b in zip(jobs, jobs[1:]):
+        if inverse:
+            assert a.full == b.ll
+        else:
+            assert a.ll == b.full
+        assert a.full != a.ll
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert sv.percentile(v, 50) == 50
+    assert sv.percentile(v, 99) == 99
+    assert sv.percentile(v, 100) == 100
+    assert sv.percentile([3.0], 99) == 3.0
+    assert math.isclose(sv.percentile(np.linspace(0, 1, 11).tolist(), 50), 0.5)
