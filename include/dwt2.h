@@ -83,6 +83,16 @@ typedef struct {
  * Returns 0 for L = 1 and for invalid sizes. */
 size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels);
 
+/* Tile id that marks a level as part of the fused tail launch. */
+#define DWT2_TILE_TAIL (-2)
+#define DWT2_TAIL_MAX 3
+#define DWT2_TAIL_AUTO_PIXELS (1 << 20)
+
+/* Number of trailing levels that dwt2_forward and dwt2_inverse fuse into
+ * one launch when called without tiles (0 when none; never 1). Returns
+ * DWT2_ERR_INVALID_ARG for sizes the transform rejects. */
+int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels);
+
 /* Forward L-level 2-D DWT.
  *   src   : the image, described by *src_d (read only).
  *   coef  : the Mallat-layout coefficients, described by *coef_d; same width,
@@ -90,13 +100,21 @@ size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels);
  *   wavelet, boundary, scheme : enum values above.
  *   levels: 1..16; width and height must be divisible by 2^levels.
  *   tiles : NULL to let the library choose, else `levels` tile ids
- *           (0 <= id < dwt2_tile_config_count()), one per level.
+ *           (0 <= id < dwt2_tile_config_count()), one per level, or
+ *           DWT2_TILE_TAIL for each of the last 2..DWT2_TAIL_MAX levels:
+ *           those run fused in one launch (one workgroup computes every
+ *           fused level for its block; intermediate low-low bands stay in
+ *           LDS). Results are identical either way. Without `tiles` the
+ *           library fuses the trailing levels whose input has at most
+ *           DWT2_TAIL_AUTO_PIXELS pixels, when there are two or more.
  *   workspace, workspace_bytes : FP32 scratch of at least
  *           dwt2_workspace_bytes(width, height, levels) bytes; may be NULL
  *           when that is 0. Must not overlap src or coef.
  *   level_events : NULL, or 2*levels hipEvent_t handles; events
  *           [2j] and [2j+1] are recorded on `stream` before and after the
- *           launch of level j+1, for per-kernel timing.
+ *           launch of level j+1, for per-kernel timing. For fused levels
+ *           the first fused level's pair brackets the fused launch and the
+ *           other fused levels' pairs are both recorded after it.
  *   stream: hipStream_t to enqueue on.
  * Returns a dwt2_status. */
 int dwt2_forward(const void *src, const dwt2_desc *src_d,

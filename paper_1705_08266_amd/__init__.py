@@ -72,6 +72,9 @@ def _events_arg(events, levels):
         return None
     if len(events) != 2 * levels:
         raise ValueError("need two events per level")
+    for e in events:
+        if not e.cuda_event:     # PyTorch creates the HIP event on its first record
+            e.record()
     return (ctypes.c_void_p * (2 * levels))(*[e.cuda_event for e in events])
 
 
@@ -172,6 +175,13 @@ def tile_configs(wavelet="cdf97"):
         _lib.check(lib.dwt2_tile_config_info(t, _wavelet(wavelet), *[ctypes.byref(a) for a in v]))
         out.append((t, *[a.value for a in v]))
     return out
+
+
+def fused_levels(width: int, height: int, levels: int) -> int:
+    """Trailing levels the library runs as one fused launch by default."""
+    n = int(load().dwt2_fused_levels(width, height, levels))
+    _lib.check(min(n, 0), "dwt2_fused_levels")
+    return n
 
 
 def default_tile(width, height, wavelet="cdf97", scheme="nonseparable", dtype=_lib.F32):

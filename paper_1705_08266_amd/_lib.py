@@ -16,6 +16,9 @@ CDF97, CDF53 = 0, 1
 EXT_WHOLE_SAMPLE_SYMMETRIC = 0
 F32, F16, BF16 = 0, 1, 2
 NONSEPARABLE, SEPARABLE = 0, 1
+TILE_TAIL = -2            # tiles[j] of a level that runs in the fused tail launch
+TAIL_MAX = 3
+TAIL_AUTO_PIXELS = 1 << 20
 
 # Every function declared in include/dwt2.h: name -> (restype, argtypes)
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -74,6 +77,7 @@ SIGNATURES = {
     "dwt2_inverse_batch": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_forward_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_inverse_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
+    "dwt2_fused_levels": (ctypes.c_int, [_i32, _i32, _i32]),
     "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dwt2_last_hip_error": (ctypes.c_int, []),
     "dwt2_version": (ctypes.c_int, []),

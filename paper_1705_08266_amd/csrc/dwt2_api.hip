@@ -137,6 +137,75 @@ const InvBatchTable &inv_batch_table(int dt) {
     return dt == DWT2_F32 ? kInvBatchF32 : dt == DWT2_F16 ? kInvBatchF16 : kInvBatchBF16;
 }
 
+const FwdTailTable &fwd_tail_table(int dt) {
+    return dt == DWT2_F32 ? kFwdTailF32 : dt == DWT2_F16 ? kFwdTailF16 : kFwdTailBF16;
+}
+const InvTailTable &inv_tail_table(int dt) {
+    return dt == DWT2_F32 ? kInvTailF32 : dt == DWT2_F16 ? kInvTailF16 : kInvTailBF16;
+}
+
+static_assert(DWT2_TAIL_MAX == kTailMax, "header and kernels agree on the fused depth");
+
+// First fused level (1-based) of an L-level transform, or levels + 1 when no
+// level is fused. With explicit tiles the DWT2_TILE_TAIL entries must form a
+// suffix of 2..kTailMax levels (else -1).
+int tail_start(int W, int H, int levels, const int32_t *tiles) {
+    if (tiles) {
+        int k = levels + 1;
+        while (k > 1 && tiles[k - 2] == DWT2_TILE_TAIL) --k;
+        for (int j = 1; j < k; ++j)
+            if (tiles[j - 1] == DWT2_TILE_TAIL) return -1;
+        const int F = levels + 1 - k;
+        if (F == 0) return k;
+        return (F >= 2 && F <= kTailMax) ? k : -1;
+    }
+    int k = levels + 1;
+    while (k > 1 && levels + 2 - k <= kTailMax &&
+           (int64_t)(W >> (k - 2)) * (int64_t)(H >> (k - 2)) <= DWT2_TAIL_AUTO_PIXELS)
+        --k;
+    return levels + 1 - k >= 2 ? k : levels + 1;
+}
+
+// Block side and region extensions of a fused tail (see dwt2_tail.hpp).
+// Forward: level m = 0 is the finest; inverse: m = 0 is the coarsest.
+struct TailPlan {
+    int B, e[kTailMax];
+};
+
+TailPlan plan_fwd_tail(int F, int wavelet) {
+    const int R = wavelet == DWT2_CDF97 ? 2 : 1;
+    TailPlan t;
+    t.e[F - 1] = 0;
+    for (int m = F - 2; m >= 0; --m) t.e[m] = 2 * t.e[m + 1] + 2 * R;
+    int B = 1 << 30;
+    for (int m = 0; m < F; ++m) {
+        int lim = kTailWin - 2 * R;                       // the register window
+        if (m < F - 1 && lim > kTailBufSide) lim = kTailBufSide;   // the LDS region
+        const int b = (lim - 2 * t.e[m]) >> (F - 1 - m);
+        if (b < B) B = b;
+    }
+    t.B = B;
+    return t;
+}
+
+TailPlan plan_inv_tail(int F, int wavelet) {
+    const int R = wavelet == DWT2_CDF97 ? 2 : 1;
+    TailPlan t;
+    t.e[F - 1] = 0;
+    for (int m = F - 2; m >= 0; --m) t.e[m] = (t.e[m + 1] + R + 1) / 2;
+    int B = 1 << 30;
+    for (int m = 0; m < F; ++m) {
+        int b = (kTailWin - 2 * R - 2 * t.e[m]) >> m;
+        if (m < F - 1) {
+            const int bl = (kTailBufSide / 2 - 2 * t.e[m]) >> m;   // output pixels in LDS
+            if (bl < b) b = bl;
+        }
+        if (b < B) B = b;
+    }
+    t.B = B;
+    return t;
+}
+
 // Size class of a level whose input is width x height pixels.
 int size_class(int width, int height) {
     const int64_t px = (int64_t)width * height;
@@ -262,7 +331,8 @@ int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_de
     if (xd->pitch < W || yd->pitch < W) return DWT2_ERR_INVALID_ARG;
     if (tiles) {
         for (int j = 0; j < levels; ++j)
-            if (tiles[j] < -1 || tiles[j] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+            if (tiles[j] < DWT2_TILE_TAIL || tiles[j] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+        if (tail_start(W, H, levels, tiles) < 0) return DWT2_ERR_UNSUPPORTED;
     }
     const Span sx = span_of(x, H, W, xd->pitch, xd->dtype);
     const Span sy = span_of(y, H, W, yd->pitch, yd->dtype);
@@ -346,6 +416,13 @@ size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels) {
     return n * sizeof(float);
 }
 
+int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels) {
+    if (levels < 1 || levels > 16 || width < 2 || height < 2 ||
+        (width % (1 << levels)) != 0 || (height % (1 << levels)) != 0)
+        return DWT2_ERR_INVALID_ARG;
+    return levels + 1 - tail_start(width, height, levels, nullptr);
+}
+
 int dwt2_tile_config_count(void) { return kNumTiles; }
 
 int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind, int32_t *quads_per_lane,
@@ -407,6 +484,8 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2
                               : nullptr};
     char *cbase = static_cast<char *>(coef);
     const int64_t cp = coef_d->pitch;
+    const int k = tail_start(W, H, levels, tiles);
+    FwdTail tail;
     for (int j = 1; j <= levels; ++j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
         const void *in = j == 1 ? src : (const void *)ws[(j - 2) & 1];
@@ -418,12 +497,37 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2
         void *ll = j == levels ? (void *)coef : (void *)ws[(j - 1) & 1];
         const int64_t ll_pitch = j == levels ? cp : w / 2;
         const int ll_dt = j == levels ? T : DWT2_F32;
+        if (j >= k) {   // fused: parameters only (the kernel reads in of the first, ll of the last)
+            tail.lv[j - k] = fwd_params(in, in_pitch, in_dt, w, h, ll, ll_pitch, ll_dt, hl, lh,
+                                        hh, cp, T, wavelet, 0);
+            tail.lv[j - k].vec_in = aligned(in, in_pitch, in_dt, 2);
+            continue;
+        }
         const int tile = tiles ? tiles[j - 1] : -1;
         if ((st = record(level_events, 2 * (j - 1), s))) return st;
         st = fwd_level(in, in_pitch, in_dt, w, h, ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, wavelet,
                        scheme, tile, s);
         if (st) return st;
         if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
+    }
+    if (k <= levels) {
+        const int F = levels + 1 - k;
+        const TailPlan pl = plan_fwd_tail(F, wavelet);
+        tail.F = F;
+        tail.B = pl.B;
+        for (int m = 0; m < F; ++m) tail.e[m] = pl.e[m];
+        const FwdParams &last = tail.lv[F - 1];
+        tail.blocks_x = (last.nqx + pl.B - 1) / pl.B;
+        const int grid = tail.blocks_x * ((last.nqy + pl.B - 1) / pl.B);
+        if ((st = record(level_events, 2 * (k - 1), s))) return st;
+        const hipError_t e =
+            fwd_tail_table(T)[wavelet][scheme][k > 1 || T == DWT2_F32](tail, grid, s);
+        if (e != hipSuccess) return hip_fail(e);
+        if ((st = record(level_events, 2 * (k - 1) + 1, s))) return st;
+        for (int j = k + 1; j <= levels; ++j) {
+            if ((st = record(level_events, 2 * (j - 1), s))) return st;
+            if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
+        }
     }
     return DWT2_OK;
 }
@@ -443,6 +547,8 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
                               : nullptr};
     const char *cbase = static_cast<const char *>(coef);
     const int64_t cp = coef_d->pitch;
+    const int k = tail_start(W, H, levels, tiles);
+    InvTail tail;
     for (int j = levels; j >= 1; --j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
         const void *ll = j == levels ? coef : (const void *)ws[(j - 1) & 1];
@@ -454,6 +560,32 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
         void *out = j == 1 ? dst : (void *)ws[(j - 2) & 1];
         const int64_t out_pitch = j == 1 ? dst_d->pitch : w;
         const int out_dt = j == 1 ? T : DWT2_F32;
+        if (j >= k) {   // fused: collected here, launched once after the loop body below
+            InvParams &p = tail.lv[levels - j];
+            p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out, out_pitch, out_dt, w, h,
+                           wavelet, 0);
+            p.vec_ll = aligned(ll, ll_pitch, ll_dt, 1);
+            p.vec_band = aligned(hl, cp, T, 1) && aligned(lh, cp, T, 1) && aligned(hh, cp, T, 1);
+            if (j > k) continue;
+            const int F = levels + 1 - k;
+            const TailPlan pl = plan_inv_tail(F, wavelet);
+            tail.F = F;
+            tail.B = pl.B;
+            for (int m = 0; m < F; ++m) tail.e[m] = pl.e[m];
+            const InvParams &first = tail.lv[0];
+            tail.blocks_x = (first.nqx + pl.B - 1) / pl.B;
+            const int grid = tail.blocks_x * ((first.nqy + pl.B - 1) / pl.B);
+            if ((st = record(level_events, 2 * (levels - 1), s))) return st;
+            const hipError_t e =
+                inv_tail_table(T)[wavelet][scheme][k > 1 || T == DWT2_F32](tail, grid, s);
+            if (e != hipSuccess) return hip_fail(e);
+            if ((st = record(level_events, 2 * (levels - 1) + 1, s))) return st;
+            for (int jj = levels - 1; jj >= k; --jj) {
+                if ((st = record(level_events, 2 * (jj - 1), s))) return st;
+                if ((st = record(level_events, 2 * (jj - 1) + 1, s))) return st;
+            }
+            continue;
+        }
         const int tile = tiles ? tiles[j - 1] : -1;
         if ((st = record(level_events, 2 * (j - 1), s))) return st;
         st = inv_level(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out, out_pitch, out_dt, w, h,

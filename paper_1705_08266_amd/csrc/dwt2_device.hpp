@@ -219,10 +219,18 @@ __device__ __forceinline__ void store_vec(rsrc_t r, uint32_t off, const float (&
 // Whole-sample symmetric extension of an n-sample axis (n >= 2), periodic
 // with period 2n-2: the index of the sample that position x stands for.
 __device__ __forceinline__ int mirror(int x, int n) {
+    if (x < 0) x = -x;                 // the extension is even about 0
+    if (x < n) return x;
     const int period = 2 * n - 2;
-    x %= period;
-    if (x < 0) x += period;
+    if (x >= period) x %= period;      // only for windows wider than the level
     return x < n ? x : period - x;
+}
+
+// True when every lane of the wavefront has `c` set: a wavefront-uniform
+// branch condition. Loads of the two paths then never share an exec mask,
+// so the vector path's loads of all rows stay in flight together.
+__device__ __forceinline__ bool wave_all(bool c) {
+    return __builtin_amdgcn_ballot_w64(!c) == 0;
 }
 
 // ---- cross-lane shifts (DPP, wavefront-wide) ----------------------------------

@@ -75,19 +75,18 @@ __device__ __forceinline__ int block_tile() {
 }
 
 // ---- forward: load / store of one tile ----------------------------------------
-template <int QPL, int ROWS, typename G, typename TIN>
-__device__ __forceinline__ void fwd_load(Quads<ROWS, QPL> &q, const FwdParams &prm, int t,
-                                         int lane, int wave) {
-    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
-    const int qx0 = tx * G::OX - G::HX + lane * QPL;   // first quad column of the lane
-    const int qy0 = ty * G::OY - G::HY + wave * ROWS;  // first quad row of the lane
+// The lane's quads start at quad column qx0 and quad row qy0 of the level;
+// positions outside the level are read through the symmetric extension.
+template <int QPL, int ROWS, typename TIN>
+__device__ __forceinline__ void fwd_load_at(Quads<ROWS, QPL> &q, const FwdParams &prm, int qx0,
+                                            int qy0) {
     const TIN *in = static_cast<const TIN *>(prm.in);
     const int px0 = 2 * qx0;
     const bool lane_inside = prm.vec_in && px0 >= 0 && px0 + 2 * QPL <= prm.w;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int py = 2 * (qy0 + r);
-        if (lane_inside && py >= 0 && py + 2 <= prm.h) {
+        if (wave_all(lane_inside && py >= 0 && py + 2 <= prm.h)) {
             float e[2 * QPL], o[2 * QPL];
             const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TIN);
             const uint32_t off = (uint32_t)px0 * (uint32_t)sizeof(TIN);
@@ -110,6 +109,14 @@ __device__ __forceinline__ void fwd_load(Quads<ROWS, QPL> &q, const FwdParams &p
             }
         }
     }
+}
+
+template <int QPL, int ROWS, typename G, typename TIN>
+__device__ __forceinline__ void fwd_load(Quads<ROWS, QPL> &q, const FwdParams &prm, int t,
+                                         int lane, int wave) {
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
+    fwd_load_at<QPL, ROWS, TIN>(q, prm, tx * G::OX - G::HX + lane * QPL,
+                                ty * G::OY - G::HY + wave * ROWS);
 }
 
 template <int WV, int QPL, int ROWS, int WAVES, typename G, typename TLL, typename TB>
@@ -195,12 +202,9 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
 // Outside the level, each polyphase component is extended through the
 // symmetric extension of the pixel grid it lives on: quad (i, j) component b
 // stands for pixel (2i+1, 2j), and so on.
-template <int QPL, int ROWS, typename G, typename TLL, typename TB>
-__device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &prm, int t,
-                                         int lane, int wave) {
-    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
-    const int qx0 = tx * G::OX - G::HX + lane * QPL;
-    const int qy0 = ty * G::OY - G::HY + wave * ROWS;
+template <int QPL, int ROWS, typename TLL, typename TB>
+__device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams &prm, int qx0,
+                                            int qy0) {
     const TLL *ll = static_cast<const TLL *>(prm.ll);
     const TB *hl = static_cast<const TB *>(prm.hl);
     const TB *lh = static_cast<const TB *>(prm.lh);
@@ -209,7 +213,7 @@ __device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &p
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int gy = qy0 + r;
-        if (lane_inside && gy >= 0 && gy < prm.nqy) {
+        if (wave_all(lane_inside && gy >= 0 && gy < prm.nqy)) {
             const int64_t ob = (int64_t)gy * prm.band_pitch;
             const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
             const uint32_t offb = (uint32_t)qx0 * (uint32_t)sizeof(TB);
@@ -233,6 +237,14 @@ __device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &p
             }
         }
     }
+}
+
+template <int QPL, int ROWS, typename G, typename TLL, typename TB>
+__device__ __forceinline__ void inv_load(Quads<ROWS, QPL> &q, const InvParams &prm, int t,
+                                         int lane, int wave) {
+    const int ty = t / prm.tiles_x, tx = t - (t / prm.tiles_x) * prm.tiles_x;
+    inv_load_at<QPL, ROWS, TLL, TB>(q, prm, tx * G::OX - G::HX + lane * QPL,
+                                    ty * G::OY - G::HY + wave * ROWS);
 }
 
 template <int QPL, int ROWS, int WAVES, typename G, typename TOUT>

@@ -6,6 +6,7 @@
 
 #include "dwt2_kernels.hpp"
 #include "dwt2_stream.hpp"
+#include "dwt2_tail.hpp"
 
 namespace dwt2 {
 
@@ -191,10 +192,49 @@ constexpr InvTable make_inv_table() {
              {inv_types<T, CDF53, NONSEP>(), inv_types<T, CDF53, SEP>()}}};
 }
 
+// Fused tails. Forward index [wavelet][scheme][input of the finest fused
+// level is FP32]; inverse [wavelet][scheme][output of the finest fused level
+// is FP32]. The pyramid (bands and the coarsest LL) is in the storage type.
+using FwdTailLauncher = hipError_t (*)(const FwdTail &, int, hipStream_t);
+using InvTailLauncher = hipError_t (*)(const InvTail &, int, hipStream_t);
+
+template <int WV, int SCH, typename TIN, typename T>
+hipError_t launch_fwd_tail(const FwdTail &t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_tail_kernel<WV, SCH, TIN, T, T>), dim3(grid), dim3(64 * kTailWaves),
+                       0, s, t);
+    return hipGetLastError();
+}
+template <int WV, int SCH, typename T, typename TOUT>
+hipError_t launch_inv_tail(const InvTail &t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((inv_tail_kernel<WV, SCH, T, T, TOUT>), dim3(grid), dim3(64 * kTailWaves),
+                       0, s, t);
+    return hipGetLastError();
+}
+
+using FwdTailTable = std::array<std::array<std::array<FwdTailLauncher, 2>, 2>, 2>;
+using InvTailTable = std::array<std::array<std::array<InvTailLauncher, 2>, 2>, 2>;
+
+template <typename T>
+constexpr FwdTailTable make_fwd_tail_table() {
+    return {{{{{&launch_fwd_tail<CDF97, NONSEP, T, T>, &launch_fwd_tail<CDF97, NONSEP, float, T>},
+               {&launch_fwd_tail<CDF97, SEP, T, T>, &launch_fwd_tail<CDF97, SEP, float, T>}}},
+             {{{&launch_fwd_tail<CDF53, NONSEP, T, T>, &launch_fwd_tail<CDF53, NONSEP, float, T>},
+               {&launch_fwd_tail<CDF53, SEP, T, T>, &launch_fwd_tail<CDF53, SEP, float, T>}}}}};
+}
+template <typename T>
+constexpr InvTailTable make_inv_tail_table() {
+    return {{{{{&launch_inv_tail<CDF97, NONSEP, T, T>, &launch_inv_tail<CDF97, NONSEP, T, float>},
+               {&launch_inv_tail<CDF97, SEP, T, T>, &launch_inv_tail<CDF97, SEP, T, float>}}},
+             {{{&launch_inv_tail<CDF53, NONSEP, T, T>, &launch_inv_tail<CDF53, NONSEP, T, float>},
+               {&launch_inv_tail<CDF53, SEP, T, T>, &launch_inv_tail<CDF53, SEP, T, float>}}}}};
+}
+
 // Defined in one translation unit per storage type and direction.
 extern FwdTable kFwdF32, kFwdF16, kFwdBF16;
 extern InvTable kInvF32, kInvF16, kInvBF16;
 extern FwdBatchTable kFwdBatchF32, kFwdBatchF16, kFwdBatchBF16;
 extern InvBatchTable kInvBatchF32, kInvBatchF16, kInvBatchBF16;
+extern FwdTailTable kFwdTailF32, kFwdTailF16, kFwdTailBF16;
+extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
 
 }  // namespace dwt2

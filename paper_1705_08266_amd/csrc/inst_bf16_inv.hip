@@ -4,4 +4,5 @@
 namespace dwt2 {
 InvTable kInvBF16 = make_inv_table<bf16_t>();
 InvBatchTable kInvBatchBF16 = make_inv_batch_table<bf16_t>();
+InvTailTable kInvTailBF16 = make_inv_tail_table<bf16_t>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 namespace dwt2 {
 FwdTable kFwdF16 = make_fwd_table<__half>();
 FwdBatchTable kFwdBatchF16 = make_fwd_batch_table<__half>();
+FwdTailTable kFwdTailF16 = make_fwd_tail_table<__half>();
 }  // namespace dwt2

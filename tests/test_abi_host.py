@@ -112,6 +112,30 @@ def test_forward_argument_errors():
                 levels=2) == E                                   # 66 % 4 != 0
 
 
+def test_fused_tail_tile_ids():
+    """DWT2_TILE_TAIL must mark a suffix of 2..DWT2_TAIL_MAX levels."""
+    U, W, T = _lib.ERR_UNSUPPORTED, _lib.ERR_WORKSPACE, _lib.TILE_TAIL
+
+    def tiles(*ids):
+        return (ctypes.c_int32 * len(ids))(*ids)
+
+    assert _fwd(levels=3, tiles=tiles(T, 1, T)) == U          # not a suffix
+    assert _fwd(levels=3, tiles=tiles(1, 1, T)) == U          # a single fused level
+    assert _fwd(levels=4, tiles=tiles(T, T, T, T)) == U       # deeper than DWT2_TAIL_MAX
+    assert _fwd(levels=3, tiles=tiles(1, -3, 1)) == U         # unknown negative id
+    # accepted: the call goes on to the workspace check
+    assert _fwd(levels=3, tiles=tiles(1, T, T)) == W
+    assert _fwd(levels=3, tiles=tiles(T, T, T)) == W
+    assert _lib.TAIL_MAX == 3
+    import paper_1705_08266_amd as dwt
+    assert dwt.fused_levels(4096, 4096, 5) == 3            # levels 3..5 (1024^2 and below)
+    assert dwt.fused_levels(7680, 4320, 5) == 2            # levels 4..5
+    assert dwt.fused_levels(16384, 16384, 5) == 0          # only level 5 is small
+    assert dwt.fused_levels(512, 512, 1) == 0
+    assert dwt.fused_levels(256, 384, 3) == 3
+    assert _lib.load().dwt2_fused_levels(64, 64, 7) == _lib.ERR_INVALID_ARG
+
+
 def test_inverse_argument_errors():
     lib = _lib.load()
     d = _lib.Desc(32, 32, 32, _lib.F32)
