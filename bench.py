@@ -54,6 +54,25 @@ def level_bytes(W, H, levels, es_store):
     return out
 
 
+def executed_bytes(W, H, levels, es_store, fused):
+    """Algorithmic bytes per direction of the launches actually made: the
+    per-level launches as in level_bytes, and for the last `fused` levels one
+    read of the first fused level's input plus one write of every fused
+    level's detail bands and the final LL (their intermediate LL stays on
+    chip)."""
+    lb = level_bytes(W, H, levels, es_store)
+    if fused < 2:
+        return sum(lb)
+    k = levels - fused + 1
+    w, h = W >> (k - 1), H >> (k - 1)
+    tail = w * h * (es_store if k == 1 else 4)
+    for j in range(k, levels + 1):
+        px = (W >> (j - 1)) * (H >> (j - 1))
+        tail += (px // 4) * 3 * es_store
+    tail += (W >> levels) * (H >> levels) * es_store
+    return sum(lb[:k - 1]) + tail
+
+
 def make_image(W, H, kind, seed):
     import synthetic
     if kind == "sinusoid":
@@ -81,10 +100,14 @@ def run_gpu(args, x_np, scheme):
         ws = dwt.make_workspace(W, H, L, dev)
         sets.append((src, coef, rec, ws))
 
+    # --fuse off: one launch per level (the library's per-level choice)
+    chain_tiles = [dwt.default_tile(W >> j, H >> j) for j in range(L)] if args.fuse == "off" \
+        else None
+
     def step(k):
         src, coef, rec, ws = sets[k % len(sets)]
-        dwt.forward(src, args.wavelet, L, scheme, out=coef, workspace=ws)
-        dwt.inverse(coef, args.wavelet, L, scheme, out=rec, workspace=ws)
+        dwt.forward(src, args.wavelet, L, scheme, out=coef, workspace=ws, tiles=chain_tiles)
+        dwt.inverse(coef, args.wavelet, L, scheme, out=rec, workspace=ws, tiles=chain_tiles)
 
     for k in range(args.warmup):
         step(k)
@@ -127,7 +150,7 @@ def run_gpu(args, x_np, scheme):
     # bracketed by events on the launch stream, buffers rotating
     R = 40
     fwd_ms, inv_ms = [], []
-    fused = dwt.fused_levels(W, H, L)
+    fused = dwt.fused_levels(W, H, L) if args.fuse == "auto" else 0
     k_tail = L + 1 - fused if fused else L + 1
     for j in range(1, k_tail + 1 if fused else L + 1):
         w, h = W >> (j - 1), H >> (j - 1)
@@ -380,6 +403,8 @@ def main():
     ap.add_argument("--eager", action="store_true",
                     help="launch every step from the host instead of replaying a graph")
     ap.add_argument("--requests", type=int, default=400, help="requests in the serve workload")
+    ap.add_argument("--fuse", default="auto", choices=["auto", "off"],
+                    help="auto: the library fuses the coarse levels; off: one launch per level")
     ap.add_argument("--workload", default="image", choices=["image", "batch", "serve"],
                     help="image: one image forward+inverse (headline); batch: many uneven "
                          "images, batched forward")
@@ -464,10 +489,11 @@ def main():
                               f"{args.wavelet} forward+inverse, {L} levels, "
                               f"{args.scheme} lifting, {args.sets} rotating buffer sets"),
                     width=W, height=H, levels=L, wavelet=args.wavelet, scheme=args.scheme,
-                    storage=args.dtype, buffer_sets=args.sets),
+                    storage=args.dtype, buffer_sets=args.sets, fuse=args.fuse),
         roofline=roofline,
         hbm_frac_whole_step=round(alg_bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         algorithmic_bytes_per_step=alg_bytes_step,
+        executed_bytes_per_step=2 * executed_bytes(W, H, L, es, len(main_run["fused_levels"])),
         level_ms=dict(forward=rounded(main_run["fwd_level_ms"]),
                       inverse=rounded(main_run["inv_level_ms"])),
         fused_levels=main_run["fused_levels"],

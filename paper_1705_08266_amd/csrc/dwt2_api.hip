@@ -521,7 +521,7 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2
         const int grid = tail.blocks_x * ((last.nqy + pl.B - 1) / pl.B);
         if ((st = record(level_events, 2 * (k - 1), s))) return st;
         const hipError_t e =
-            fwd_tail_table(T)[wavelet][scheme][k > 1 || T == DWT2_F32](tail, grid, s);
+            fwd_tail_table(T)[wavelet][scheme][F - 2][k > 1 || T == DWT2_F32](tail, grid, s);
         if (e != hipSuccess) return hip_fail(e);
         if ((st = record(level_events, 2 * (k - 1) + 1, s))) return st;
         for (int j = k + 1; j <= levels; ++j) {
@@ -566,6 +566,7 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
                            wavelet, 0);
             p.vec_ll = aligned(ll, ll_pitch, ll_dt, 1);
             p.vec_band = aligned(hl, cp, T, 1) && aligned(lh, cp, T, 1) && aligned(hh, cp, T, 1);
+            p.vec_out = aligned(out, out_pitch, out_dt, 2);
             if (j > k) continue;
             const int F = levels + 1 - k;
             const TailPlan pl = plan_inv_tail(F, wavelet);
@@ -577,7 +578,7 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
             const int grid = tail.blocks_x * ((first.nqy + pl.B - 1) / pl.B);
             if ((st = record(level_events, 2 * (levels - 1), s))) return st;
             const hipError_t e =
-                inv_tail_table(T)[wavelet][scheme][k > 1 || T == DWT2_F32](tail, grid, s);
+                inv_tail_table(T)[wavelet][scheme][F - 2][k > 1 || T == DWT2_F32](tail, grid, s);
             if (e != hipSuccess) return hip_fail(e);
             if ((st = record(level_events, 2 * (levels - 1) + 1, s))) return st;
             for (int jj = levels - 1; jj >= k; --jj) {

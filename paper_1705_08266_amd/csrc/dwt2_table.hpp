@@ -192,41 +192,49 @@ constexpr InvTable make_inv_table() {
              {inv_types<T, CDF53, NONSEP>(), inv_types<T, CDF53, SEP>()}}};
 }
 
-// Fused tails. Forward index [wavelet][scheme][input of the finest fused
-// level is FP32]; inverse [wavelet][scheme][output of the finest fused level
-// is FP32]. The pyramid (bands and the coarsest LL) is in the storage type.
+// Fused tails. Forward index [wavelet][scheme][fused levels - 2][input of the
+// finest fused level is FP32]; inverse [wavelet][scheme][fused levels - 2]
+// [output of the finest fused level is FP32]. The pyramid (bands and the
+// coarsest LL) is in the storage type.
 using FwdTailLauncher = hipError_t (*)(const FwdTail &, int, hipStream_t);
 using InvTailLauncher = hipError_t (*)(const InvTail &, int, hipStream_t);
 
-template <int WV, int SCH, typename TIN, typename T>
+template <int WV, int SCH, int F, typename TIN, typename T>
 hipError_t launch_fwd_tail(const FwdTail &t, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((fwd_tail_kernel<WV, SCH, TIN, T, T>), dim3(grid), dim3(64 * kTailWaves),
-                       0, s, t);
+    hipLaunchKernelGGL((fwd_tail_kernel<WV, SCH, F, TIN, T, T>), dim3(grid),
+                       dim3(64 * kTailWaves), 0, s, t);
     return hipGetLastError();
 }
-template <int WV, int SCH, typename T, typename TOUT>
+template <int WV, int SCH, int F, typename T, typename TOUT>
 hipError_t launch_inv_tail(const InvTail &t, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((inv_tail_kernel<WV, SCH, T, T, TOUT>), dim3(grid), dim3(64 * kTailWaves),
-                       0, s, t);
+    hipLaunchKernelGGL((inv_tail_kernel<WV, SCH, F, T, T, TOUT>), dim3(grid),
+                       dim3(64 * kTailWaves), 0, s, t);
     return hipGetLastError();
 }
 
-using FwdTailTable = std::array<std::array<std::array<FwdTailLauncher, 2>, 2>, 2>;
-using InvTailTable = std::array<std::array<std::array<InvTailLauncher, 2>, 2>, 2>;
+static_assert(kTailMax == 3, "tail tables cover 2 and 3 fused levels");
+using FwdTailTable = std::array<std::array<std::array<std::array<FwdTailLauncher, 2>, 2>, 2>, 2>;
+using InvTailTable = std::array<std::array<std::array<std::array<InvTailLauncher, 2>, 2>, 2>, 2>;
 
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<FwdTailLauncher, 2>, 2> fwd_tail_depths() {
+    return {{{&launch_fwd_tail<WV, SCH, 2, T, T>, &launch_fwd_tail<WV, SCH, 2, float, T>},
+             {&launch_fwd_tail<WV, SCH, 3, T, T>, &launch_fwd_tail<WV, SCH, 3, float, T>}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<InvTailLauncher, 2>, 2> inv_tail_depths() {
+    return {{{&launch_inv_tail<WV, SCH, 2, T, T>, &launch_inv_tail<WV, SCH, 2, T, float>},
+             {&launch_inv_tail<WV, SCH, 3, T, T>, &launch_inv_tail<WV, SCH, 3, T, float>}}};
+}
 template <typename T>
 constexpr FwdTailTable make_fwd_tail_table() {
-    return {{{{{&launch_fwd_tail<CDF97, NONSEP, T, T>, &launch_fwd_tail<CDF97, NONSEP, float, T>},
-               {&launch_fwd_tail<CDF97, SEP, T, T>, &launch_fwd_tail<CDF97, SEP, float, T>}}},
-             {{{&launch_fwd_tail<CDF53, NONSEP, T, T>, &launch_fwd_tail<CDF53, NONSEP, float, T>},
-               {&launch_fwd_tail<CDF53, SEP, T, T>, &launch_fwd_tail<CDF53, SEP, float, T>}}}}};
+    return {{{fwd_tail_depths<T, CDF97, NONSEP>(), fwd_tail_depths<T, CDF97, SEP>()},
+             {fwd_tail_depths<T, CDF53, NONSEP>(), fwd_tail_depths<T, CDF53, SEP>()}}};
 }
 template <typename T>
 constexpr InvTailTable make_inv_tail_table() {
-    return {{{{{&launch_inv_tail<CDF97, NONSEP, T, T>, &launch_inv_tail<CDF97, NONSEP, T, float>},
-               {&launch_inv_tail<CDF97, SEP, T, T>, &launch_inv_tail<CDF97, SEP, T, float>}}},
-             {{{&launch_inv_tail<CDF53, NONSEP, T, T>, &launch_inv_tail<CDF53, NONSEP, T, float>},
-               {&launch_inv_tail<CDF53, SEP, T, T>, &launch_inv_tail<CDF53, SEP, T, float>}}}}};
+    return {{{inv_tail_depths<T, CDF97, NONSEP>(), inv_tail_depths<T, CDF97, SEP>()},
+             {inv_tail_depths<T, CDF53, NONSEP>(), inv_tail_depths<T, CDF53, SEP>()}}};
 }
 
 // Defined in one translation unit per storage type and direction.

@@ -27,7 +27,10 @@
 namespace dwt2 {
 
 constexpr int kTailMax = 3;                       // most fused levels per launch
-constexpr int kTailQPL = 1, kTailRows = 8, kTailWaves = 8;
+// Few workgroups run at once in a tail launch, so each level pass is bound by
+// instruction latency: 16 wavefronts of 4 quad rows keep more work in flight
+// than 8 of 8 rows.
+constexpr int kTailQPL = 1, kTailRows = 4, kTailWaves = 16;
 constexpr int kTailWin = 64;                      // register window: 64 x 64 quads
 constexpr int kTailBufSide = 60;                  // LDS region: up to 60 x 60 values
 constexpr int kTailBuf = kTailBufSide * kTailBufSide;
@@ -62,16 +65,23 @@ __device__ __forceinline__ Region tail_region(int bx, int by, int side, int ext,
     return g;
 }
 
-// Index into an LDS region of `pw` x `ph` values with origin (x0, y0), with
-// the position clamped into the region: lanes outside the computed area read
-// some held value, and their results are never stored.
-__device__ __forceinline__ int region_index(int x, int y, int x0, int y0, int pw, int ph) {
-    const int cx = min(max(x - x0, 0), pw - 1);
-    const int cy = min(max(y - y0, 0), ph - 1);
-    return cy * pw + cx;
+// Offset of position p in an LDS region axis of n values starting at p0,
+// clamped into the region: lanes outside the computed area read some held
+// value, and their results are never stored.
+__device__ __forceinline__ int clamp_to(int p, int p0, int n) {
+    return min(max(p - p0, 0), n - 1);
 }
 
-template <int WV, int SCH, typename TIN, typename TLL, typename TB>
+// Wavefront-uniform buffer resource of one row of `n` elements of T.
+template <typename T>
+__device__ __forceinline__ rsrc_t row_rsrc(const void *base, int64_t row, int64_t pitch, int n) {
+    return make_rsrc(static_cast<const T *>(base) + row * pitch,
+                     (uint32_t)n * (uint32_t)sizeof(T));
+}
+
+// F (the number of fused levels) is a template parameter so that the level
+// loop unrolls and every level's parameters load at kernel start.
+template <int WV, int SCH, int F, typename TIN, typename TLL, typename TB>
 __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
     constexpr int QPL = kTailQPL, ROWS = kTailRows, WAVES = kTailWaves;
     constexpr int R = Wavelet<WV>::NPAIRS;
@@ -84,49 +94,50 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
     const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
     const float sHH = (float)(L::ZH * L::ZH);
     int px0 = 0, py0 = 0, pw = 1, ph = 1;       // previous level's LL region in LDS
-    for (int m = 0; m < t.F; ++m) {
+#pragma unroll
+    for (int m = 0; m < F; ++m) {
         const FwdParams &prm = t.lv[m];
-        const Region g = tail_region(bx, by, t.B << (t.F - 1 - m), t.e[m], prm.nqx, prm.nqy);
+        const Region g = tail_region(bx, by, t.B << (F - 1 - m), t.e[m], prm.nqx, prm.nqy);
         const int qx = g.cx0 - R + lane;          // the lane's quad column
         const int qy0 = g.cy0 - R + wave * ROWS;  // its first quad row
         Quads<ROWS, QPL> q;
         if (m == 0) {
             fwd_load_at<QPL, ROWS, TIN>(q, prm, qx, qy0);
         } else {
+            // the level input is the previous level's LL, held in LDS for its
+            // computed region
             const float *src = llbuf[(m - 1) & 1];
-            const int xe = mirror(2 * qx, prm.w), xo = mirror(2 * qx + 1, prm.w);
+            const int xe = clamp_to(mirror(2 * qx, prm.w), px0, pw);
+            const int xo = clamp_to(mirror(2 * qx + 1, prm.w), px0, pw);
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
-                const int ye = mirror(2 * (qy0 + r), prm.h);
-                const int yo = mirror(2 * (qy0 + r) + 1, prm.h);
-                q.a[r][0] = src[region_index(xe, ye, px0, py0, pw, ph)];
-                q.b[r][0] = src[region_index(xo, ye, px0, py0, pw, ph)];
-                q.c[r][0] = src[region_index(xe, yo, px0, py0, pw, ph)];
-                q.d[r][0] = src[region_index(xo, yo, px0, py0, pw, ph)];
+                const int ye = clamp_to(mirror(2 * (qy0 + r), prm.h), py0, ph) * pw;
+                const int yo = clamp_to(mirror(2 * (qy0 + r) + 1, prm.h), py0, ph) * pw;
+                q.a[r][0] = src[ye + xe]; q.b[r][0] = src[ye + xo];
+                q.c[r][0] = src[yo + xe]; q.d[r][0] = src[yo + xo];
             }
         }
         Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
         lift_forward<WV, SCH>(q, x);
-        const bool last = m == t.F - 1;
-        const bool own_x = qx >= g.ox0 && qx < g.ox1;
-        const bool comp_x = qx >= g.cx0 && qx < g.cx1;
+        const bool last = m == F - 1;
         const int cw = g.cx1 - g.cx0;
         float *dst = llbuf[m & 1];
-        TB *hl = static_cast<TB *>(prm.hl);
-        TB *lh = static_cast<TB *>(prm.lh);
-        TB *hh = static_cast<TB *>(prm.hh);
-        TLL *llg = static_cast<TLL *>(prm.ll);
+        // lanes outside the owned columns store nowhere
+        const uint32_t ob = (qx >= g.ox0 && qx < g.ox1) ? (uint32_t)qx * sizeof(TB) : kNoAccess;
+        const uint32_t ol = (qx >= g.ox0 && qx < g.ox1) ? (uint32_t)qx * sizeof(TLL) : kNoAccess;
+        const bool comp_x = qx >= g.cx0 && qx < g.cx1;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int gy = qy0 + r;
-            const float va = q.a[r][0] * sLL, vb = q.b[r][0] * sHL;
-            const float vc = q.c[r][0] * sHL, vd = q.d[r][0] * sHH;
-            if (own_x && gy >= g.oy0 && gy < g.oy1) {
-                const int64_t ob = (int64_t)gy * prm.band_pitch + qx;
-                hl[ob] = from_float<TB>(vb);
-                lh[ob] = from_float<TB>(vc);
-                hh[ob] = from_float<TB>(vd);
-                if (last) llg[(int64_t)gy * prm.ll_pitch + qx] = from_float<TLL>(va);
+            const float va = q.a[r][0] * sLL;
+            if (gy >= g.oy0 && gy < g.oy1) {   // wavefront-uniform
+                store_elem<TB>(row_rsrc<TB>(prm.hl, gy, prm.band_pitch, prm.nqx), ob,
+                               q.b[r][0] * sHL);
+                store_elem<TB>(row_rsrc<TB>(prm.lh, gy, prm.band_pitch, prm.nqx), ob,
+                               q.c[r][0] * sHL);
+                store_elem<TB>(row_rsrc<TB>(prm.hh, gy, prm.band_pitch, prm.nqx), ob,
+                               q.d[r][0] * sHH);
+                if (last) store_elem<TLL>(row_rsrc<TLL>(prm.ll, gy, prm.ll_pitch, prm.nqx), ol, va);
             }
             if (!last && comp_x && gy >= g.cy0 && gy < g.cy1)
                 dst[(gy - g.cy0) * cw + (qx - g.cx0)] = va;
@@ -136,7 +147,7 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
     }
 }
 
-template <int WV, int SCH, typename TLL, typename TB, typename TOUT>
+template <int WV, int SCH, int F, typename TLL, typename TB, typename TOUT>
 __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
     constexpr int QPL = kTailQPL, ROWS = kTailRows, WAVES = kTailWaves;
     constexpr int R = Wavelet<WV>::NPAIRS;
@@ -149,7 +160,8 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
     const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
     const float uHH = (float)(1.0 / (L::ZH * L::ZH));
     int px0 = 0, py0 = 0, pw = 1, ph = 1;       // previous level's output region in LDS
-    for (int m = 0; m < t.F; ++m) {
+#pragma unroll
+    for (int m = 0; m < F; ++m) {
         const InvParams &prm = t.lv[m];
         const Region g = tail_region(bx, by, t.B << m, t.e[m], prm.nqx, prm.nqy);
         const int qx = g.cx0 - R + lane;
@@ -161,20 +173,19 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
             // LL from the previous (coarser) level's output in LDS; the detail
             // bands from the pyramid. Each phase is extended on its own grid.
             const float *src = pxbuf[(m - 1) & 1];
-            const TB *hl = static_cast<const TB *>(prm.hl);
-            const TB *lh = static_cast<const TB *>(prm.lh);
-            const TB *hh = static_cast<const TB *>(prm.hh);
             const int xe = mirror(2 * qx, prm.w) >> 1;
             const int xo = (mirror(2 * qx + 1, prm.w) - 1) >> 1;
+            const int xl = clamp_to(xe, px0, pw);
+            const uint32_t oe = (uint32_t)xe * sizeof(TB), oo = (uint32_t)xo * sizeof(TB);
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 const int gy = qy0 + r;
                 const int ye = mirror(2 * gy, prm.h) >> 1;
                 const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
-                q.a[r][0] = src[region_index(xe, ye, px0, py0, pw, ph)];
-                q.b[r][0] = to_float(hl[(int64_t)ye * prm.band_pitch + xo]);
-                q.c[r][0] = to_float(lh[(int64_t)yo * prm.band_pitch + xe]);
-                q.d[r][0] = to_float(hh[(int64_t)yo * prm.band_pitch + xo]);
+                q.a[r][0] = src[clamp_to(ye, py0, ph) * pw + xl];
+                q.b[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hl, ye, prm.band_pitch, prm.nqx), oo);
+                q.c[r][0] = load_elem<TB>(row_rsrc<TB>(prm.lh, yo, prm.band_pitch, prm.nqx), oe);
+                q.d[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hh, yo, prm.band_pitch, prm.nqx), oo);
             }
         }
 #pragma unroll
@@ -183,21 +194,30 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
         }
         Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
         lift_inverse<WV, SCH>(q, x);
-        const bool last = m == t.F - 1;
+        const bool last = m == F - 1;
         const int cw = 2 * (g.cx1 - g.cx0);
         float *dst = pxbuf[m & 1];
-        TOUT *out = static_cast<TOUT *>(prm.out);
-        const bool own_x = qx >= g.ox0 && qx < g.ox1;
+        const uint32_t oo = (qx >= g.ox0 && qx < g.ox1) ? 2u * (uint32_t)qx * sizeof(TOUT)
+                                                        : kNoAccess;
         const bool comp_x = qx >= g.cx0 && qx < g.cx1;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int gy = qy0 + r;
             if (last) {
-                if (own_x && gy >= g.oy0 && gy < g.oy1) {
-                    TOUT *r0 = out + (int64_t)(2 * gy) * prm.out_pitch + 2 * qx;
-                    TOUT *r1 = r0 + prm.out_pitch;
-                    r0[0] = from_float<TOUT>(q.a[r][0]); r0[1] = from_float<TOUT>(q.b[r][0]);
-                    r1[0] = from_float<TOUT>(q.c[r][0]); r1[1] = from_float<TOUT>(q.d[r][0]);
+                if (gy >= g.oy0 && gy < g.oy1) {   // wavefront-uniform
+                    const rsrc_t r0 = row_rsrc<TOUT>(prm.out, 2 * gy, prm.out_pitch, prm.w);
+                    const rsrc_t r1 = row_rsrc<TOUT>(prm.out, 2 * gy + 1, prm.out_pitch, prm.w);
+                    if (prm.vec_out) {
+                        const float e[2] = {q.a[r][0], q.b[r][0]};
+                        const float o[2] = {q.c[r][0], q.d[r][0]};
+                        store_vec<TOUT, 2>(r0, oo, e);
+                        store_vec<TOUT, 2>(r1, oo, o);
+                    } else {
+                        store_elem<TOUT>(r0, oo, q.a[r][0]);
+                        store_elem<TOUT>(r0, oo + (uint32_t)sizeof(TOUT), q.b[r][0]);
+                        store_elem<TOUT>(r1, oo, q.c[r][0]);
+                        store_elem<TOUT>(r1, oo + (uint32_t)sizeof(TOUT), q.d[r][0]);
+                    }
                 }
             } else if (comp_x && gy >= g.cy0 && gy < g.cy1) {
                 float *p0 = dst + (2 * (gy - g.cy0)) * cw + 2 * (qx - g.cx0);
