@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = ("Gpixel/s fwd+inv CDF 9/7 DWT at 4096², 5 levels (% HBM peak); "
           "serving p50/p99")
-KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp")
+KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp", "dwt2_table.hpp", "dwt2_api.hip")
 
 
 def kernel_source_sha() -> str:

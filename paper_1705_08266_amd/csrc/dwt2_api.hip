@@ -117,11 +117,13 @@ Plan plan_level(int tile, int wavelet, int nqx, int nqy) {
     return p;
 }
 
-// Configuration choice for one level: the 128 x 16-quad tile was the fastest
-// measured configuration from 256^2 to 4096^2 levels.
+// Configuration choice for one level: the 128 x 16-quad window held by 8
+// wavefronts of 2 quad rows was the fastest measured configuration from
+// 1024^2 to 4096^2 levels in both directions (more wavefronts with fewer
+// rows each keep more loads in flight per workgroup than 4 of 4 rows).
 int pick_tile(int width, int height, int wavelet) {
     (void)width; (void)height; (void)wavelet;
-    return 1;
+    return 10;
 }
 
 const FwdTable &fwd_table(int dt) {
@@ -215,7 +217,7 @@ int size_class(int width, int height) {
     return 3;
 }
 // Default 2-D tile per size class.
-const int kClassTile[DWT2_SIZE_CLASSES] = {1, 1, 1, 1};
+const int kClassTile[DWT2_SIZE_CLASSES] = {10, 10, 10, 10};
 
 int check_level_dims(int32_t width, int32_t height) {
     if (width < 2 || height < 2 || (width & 1) || (height & 1)) return DWT2_ERR_INVALID_ARG;

@@ -37,6 +37,8 @@ constexpr TileCfg kTiles[] = {
     {CFG_STREAM, 2, 8, 4, 4},    // 7
     {CFG_STREAM, 2, 8, 4, 16},   // 8
     {CFG_STREAM, 4, 4, 4, 8},    // 9: strips of 248 quads (prefetch 2 rows)
+    {CFG_TILE, 2, 2, 8, 0},      // 10: 128 x 16, 512 threads of 2 rows
+    {CFG_TILE, 2, 3, 8, 0},      // 11: 128 x 24, 512 threads of 3 rows
 };
 constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
