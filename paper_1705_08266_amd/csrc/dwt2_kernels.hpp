@@ -75,6 +75,70 @@ __device__ __forceinline__ int block_tile() {
 }
 
 // ---- forward: load / store of one tile ----------------------------------------
+// Column access of one lane at the level edge. A lane reads E consecutive
+// elements starting at column x0; outside [0, n) each element stands for its
+// symmetric-extension mirror. The mirrored columns of E consecutive positions
+// lie within E consecutive indices, so two aligned E-element vector loads
+// (at `base` and base + E) cover them and a per-lane select rebuilds the
+// lane's values. Lanes inside the level read their E elements with the first
+// load alone (the second is dropped by the buffer hardware). Every lane
+// issues the same loads, so no load sits in a divergent or lane-dependent
+// branch: the loads of all rows stay in flight together.
+template <int E>
+struct EdgeCols {
+    uint32_t off_a, off_b;   // byte offsets of the two loads (kNoAccess: none)
+    int sel[E];              // element k comes from index sel[k] of the 2E loaded
+    bool plain;              // the lane reads its own E columns unchanged
+
+    // m[k]: the column element k stands for (in [0, n)); plain: m[k] = x0 + k.
+    template <typename T>
+    __device__ __forceinline__ static EdgeCols from(const int (&m)[E], int x0, bool plain) {
+        EdgeCols c;
+        int lo = m[0];
+#pragma unroll
+        for (int k = 1; k < E; ++k) lo = min(lo, m[k]);
+        c.plain = plain;
+        const int base = plain ? x0 : (lo & ~(E - 1));
+        c.off_a = (uint32_t)base * (uint32_t)sizeof(T);
+        c.off_b = plain ? kNoAccess : (uint32_t)(base + E) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int k = 0; k < E; ++k) c.sel[k] = plain ? k : m[k] - base;
+        return c;
+    }
+};
+
+// Element i of the 2E values (a, b), as a bitwise select: exact, and kept in
+// registers (a select chain over a runtime index would be lowered to an
+// indexed access).
+template <int E>
+__device__ __forceinline__ float pick(const float (&a)[E], const float (&b)[E], int i) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) r |= __float_as_uint(a[k]) & (0u - (uint32_t)(i == k));
+#pragma unroll
+    for (int k = 0; k < E; ++k) r |= __float_as_uint(b[k]) & (0u - (uint32_t)(i == E + k));
+    return __uint_as_float(r);
+}
+
+// Completes the loads of `n` rows for the lanes of an edge wavefront: the
+// second vector of each row, then the per-lane select. `v[r]` holds the
+// first vector on entry and the lane's elements on exit.
+template <typename T, int E, int N>
+__device__ __forceinline__ void fix_cols(const rsrc_t (&rows)[N], const EdgeCols<E> &c,
+                                         float (&v)[N][E]) {
+    float b[N][E];
+#pragma unroll
+    for (int r = 0; r < N; ++r) load_vec<T, E>(rows[r], c.off_b, b[r]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        float a[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) a[k] = v[r][k];
+#pragma unroll
+        for (int k = 0; k < E; ++k) v[r][k] = pick<E>(a, b[r], c.sel[k]);
+    }
+}
+
 // The lane's quads start at quad column qx0 and quad row qy0 of the level;
 // positions outside the level are read through the symmetric extension.
 template <int QPL, int ROWS, typename TIN>
@@ -82,24 +146,13 @@ __device__ __forceinline__ void fwd_load_at(Quads<ROWS, QPL> &q, const FwdParams
                                             int qy0) {
     const TIN *in = static_cast<const TIN *>(prm.in);
     const int px0 = 2 * qx0;
-    const bool lane_inside = prm.vec_in && px0 >= 0 && px0 + 2 * QPL <= prm.w;
+    // vector loads need aligned rows whose length is a multiple of the lane's
+    // E elements, so that no vector is partly outside the row
+    if (!prm.vec_in || (prm.w & (2 * QPL - 1)) != 0) {   // else one element at a time
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int py = 2 * (qy0 + r);
-        if (wave_all(lane_inside && py >= 0 && py + 2 <= prm.h)) {
-            float e[2 * QPL], o[2 * QPL];
-            const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TIN);
-            const uint32_t off = (uint32_t)px0 * (uint32_t)sizeof(TIN);
-            load_vec<TIN, 2 * QPL>(make_rsrc(in + (int64_t)py * prm.in_pitch, rb), off, e);
-            load_vec<TIN, 2 * QPL>(make_rsrc(in + (int64_t)(py + 1) * prm.in_pitch, rb), off, o);
-#pragma unroll
-            for (int i = 0; i < QPL; ++i) {
-                q.a[r][i] = e[2 * i]; q.b[r][i] = e[2 * i + 1];
-                q.c[r][i] = o[2 * i]; q.d[r][i] = o[2 * i + 1];
-            }
-        } else {
-            const TIN *r0 = in + (int64_t)mirror(py, prm.h) * prm.in_pitch;
-            const TIN *r1 = in + (int64_t)mirror(py + 1, prm.h) * prm.in_pitch;
+        for (int r = 0; r < ROWS; ++r) {
+            const TIN *r0 = in + (int64_t)mirror(2 * (qy0 + r), prm.h) * prm.in_pitch;
+            const TIN *r1 = in + (int64_t)mirror(2 * (qy0 + r) + 1, prm.h) * prm.in_pitch;
 #pragma unroll
             for (int i = 0; i < QPL; ++i) {
                 const int xe = mirror(px0 + 2 * i, prm.w);
@@ -107,6 +160,33 @@ __device__ __forceinline__ void fwd_load_at(Quads<ROWS, QPL> &q, const FwdParams
                 q.a[r][i] = to_float(r0[xe]); q.b[r][i] = to_float(r0[xo]);
                 q.c[r][i] = to_float(r1[xe]); q.d[r][i] = to_float(r1[xo]);
             }
+        }
+        return;
+    }
+    int m[2 * QPL];
+#pragma unroll
+    for (int k = 0; k < 2 * QPL; ++k) m[k] = mirror(px0 + k, prm.w);
+    const EdgeCols<2 * QPL> cols = EdgeCols<2 * QPL>::template from<TIN>(
+        m, px0, px0 >= 0 && px0 + 2 * QPL <= prm.w);
+    const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TIN);
+    // all rows' first vectors, then (edge wavefronts only) the completion
+    rsrc_t rows[2 * ROWS];
+    float v[2 * ROWS][2 * QPL];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int py = 2 * (qy0 + r);
+        rows[2 * r] = make_rsrc(in + (int64_t)mirror(py, prm.h) * prm.in_pitch, rb);
+        rows[2 * r + 1] = make_rsrc(in + (int64_t)mirror(py + 1, prm.h) * prm.in_pitch, rb);
+        load_vec<TIN, 2 * QPL>(rows[2 * r], cols.off_a, v[2 * r]);
+        load_vec<TIN, 2 * QPL>(rows[2 * r + 1], cols.off_a, v[2 * r + 1]);
+    }
+    if (!wave_all(cols.plain)) fix_cols<TIN>(rows, cols, v);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            q.a[r][i] = v[2 * r][2 * i]; q.b[r][i] = v[2 * r][2 * i + 1];
+            q.c[r][i] = v[2 * r + 1][2 * i]; q.d[r][i] = v[2 * r + 1][2 * i + 1];
         }
     }
 }
@@ -209,33 +289,55 @@ __device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams
     const TB *hl = static_cast<const TB *>(prm.hl);
     const TB *lh = static_cast<const TB *>(prm.lh);
     const TB *hh = static_cast<const TB *>(prm.hh);
-    const bool lane_inside = prm.vec_ll && prm.vec_band && qx0 >= 0 && qx0 + QPL <= prm.nqx;
+    // quad (i, j)'s even phase stands for pixel 2i, its odd phase for 2i+1
+    int xe[QPL], xo[QPL];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int gy = qy0 + r;
-        if (wave_all(lane_inside && gy >= 0 && gy < prm.nqy)) {
-            const int64_t ob = (int64_t)gy * prm.band_pitch;
-            const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
-            const uint32_t offb = (uint32_t)qx0 * (uint32_t)sizeof(TB);
-            load_vec<TLL, QPL>(make_rsrc(ll + (int64_t)gy * prm.ll_pitch,
-                                         (uint32_t)prm.nqx * (uint32_t)sizeof(TLL)),
-                               (uint32_t)qx0 * (uint32_t)sizeof(TLL), q.a[r]);
-            load_vec<TB, QPL>(make_rsrc(hl + ob, bb), offb, q.b[r]);
-            load_vec<TB, QPL>(make_rsrc(lh + ob, bb), offb, q.c[r]);
-            load_vec<TB, QPL>(make_rsrc(hh + ob, bb), offb, q.d[r]);
-        } else {
+    for (int i = 0; i < QPL; ++i) {
+        xe[i] = mirror(2 * (qx0 + i), prm.w) >> 1;
+        xo[i] = (mirror(2 * (qx0 + i) + 1, prm.w) - 1) >> 1;
+    }
+    if (!(prm.vec_ll && prm.vec_band) || (prm.nqx & (QPL - 1)) != 0) {   // one at a time
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int gy = qy0 + r;
             const int ye = mirror(2 * gy, prm.h) >> 1;
             const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
 #pragma unroll
             for (int i = 0; i < QPL; ++i) {
-                const int xe = mirror(2 * (qx0 + i), prm.w) >> 1;
-                const int xo = (mirror(2 * (qx0 + i) + 1, prm.w) - 1) >> 1;
-                q.a[r][i] = to_float(ll[(int64_t)ye * prm.ll_pitch + xe]);
-                q.b[r][i] = to_float(hl[(int64_t)ye * prm.band_pitch + xo]);
-                q.c[r][i] = to_float(lh[(int64_t)yo * prm.band_pitch + xe]);
-                q.d[r][i] = to_float(hh[(int64_t)yo * prm.band_pitch + xo]);
+                q.a[r][i] = to_float(ll[(int64_t)ye * prm.ll_pitch + xe[i]]);
+                q.b[r][i] = to_float(hl[(int64_t)ye * prm.band_pitch + xo[i]]);
+                q.c[r][i] = to_float(lh[(int64_t)yo * prm.band_pitch + xe[i]]);
+                q.d[r][i] = to_float(hh[(int64_t)yo * prm.band_pitch + xo[i]]);
             }
         }
+        return;
+    }
+    const bool plain = qx0 >= 0 && qx0 + QPL <= prm.nqx;
+    const EdgeCols<QPL> ce = EdgeCols<QPL>::template from<TB>(xe, qx0, plain);
+    const EdgeCols<QPL> co = EdgeCols<QPL>::template from<TB>(xo, qx0, plain);
+    const EdgeCols<QPL> cl = EdgeCols<QPL>::template from<TLL>(xe, qx0, plain);
+    const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
+    const uint32_t lb = (uint32_t)prm.nqx * (uint32_t)sizeof(TLL);
+    rsrc_t rl[ROWS], rh[ROWS], rv[ROWS], rd[ROWS];   // LL, HL, LH, HH rows
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int gy = qy0 + r;
+        const int64_t ye = mirror(2 * gy, prm.h) >> 1;
+        const int64_t yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
+        rl[r] = make_rsrc(ll + ye * prm.ll_pitch, lb);
+        rh[r] = make_rsrc(hl + ye * prm.band_pitch, bb);
+        rv[r] = make_rsrc(lh + yo * prm.band_pitch, bb);
+        rd[r] = make_rsrc(hh + yo * prm.band_pitch, bb);
+        load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
+        load_vec<TB, QPL>(rh[r], co.off_a, q.b[r]);
+        load_vec<TB, QPL>(rv[r], ce.off_a, q.c[r]);
+        load_vec<TB, QPL>(rd[r], co.off_a, q.d[r]);
+    }
+    if (!wave_all(plain)) {
+        fix_cols<TLL>(rl, cl, q.a);
+        fix_cols<TB>(rh, co, q.b);
+        fix_cols<TB>(rv, ce, q.c);
+        fix_cols<TB>(rd, co, q.d);
     }
 }
 
