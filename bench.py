@@ -150,7 +150,8 @@ def run_gpu(args, x_np, scheme):
     # bracketed by events on the launch stream, buffers rotating
     R = 40
     fwd_ms, inv_ms = [], []
-    fused = dwt.fused_levels(W, H, L) if args.fuse == "auto" else 0
+    # the exchange-ablation schemes never fuse levels
+    fused = dwt.fused_levels(W, H, L) if args.fuse == "auto" and not scheme.endswith("_lds") else 0
     k_tail = L + 1 - fused if fused else L + 1
     for j in range(1, k_tail + 1 if fused else L + 1):
         w, h = W >> (j - 1), H >> (j - 1)
@@ -400,6 +401,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-separable", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the schemes whose every neighbour exchange goes through LDS")
     ap.add_argument("--eager", action="store_true",
                     help="launch every step from the host instead of replaying a graph")
     ap.add_argument("--requests", type=int, default=400, help="requests in the serve workload")
@@ -455,6 +458,15 @@ def main():
         print("[bench] separable-lifting kernel, same protocol", file=sys.stderr, flush=True)
         sep_run = run_gpu(args, x, "separable")
 
+    ablation = {}
+    if not args.no_ablation and args.dtype == "f32" and args.scheme in ("nonseparable", "separable"):
+        # both schemes with every neighbour exchange through LDS and a barrier
+        # (the setting of the paper's barrier argument): 2 vs 4 barriers per pair
+        for sch in ("nonseparable_lds", "separable_lds"):
+            print(f"[bench] exchange ablation: {sch}", file=sys.stderr, flush=True)
+            r = run_gpu(args, x, sch)
+            ablation[sch] = r
+
     es = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     lb = level_bytes(W, H, L, es)
     K = args.steps
@@ -509,6 +521,15 @@ def main():
             level1_gbs=round(lb[0] / (s1 * 1e-3) / 1e9, 1),
             level_ms=dict(forward=rounded(sep_run["fwd_level_ms"]),
                           inverse=rounded(sep_run["inv_level_ms"])))
+
+    if ablation:
+        result["exchange_ablation"] = {
+            sch: dict(value=round(W * H / (r["total_ms"] / K * 1e-3) / 1e9, 3),
+                      ms_per_step=round(r["total_ms"] / K, 5),
+                      level1_ms=dict(forward=round(r["fwd_level_ms"][0], 5),
+                                     inverse=round(r["inv_level_ms"][0], 5)),
+                      barriers_per_lifting_pair=2 if sch.startswith("nonsep") else 4)
+            for sch, r in ablation.items()}
 
     x_stored = main_run["stored"].astype(np.float64)
     scale = float(np.abs(x_stored).max())

@@ -67,7 +67,20 @@ typedef enum { DWT2_F32 = 0, DWT2_F16 = 1, DWT2_BF16 = 2 } dwt2_dtype;
 
 /* NONSEPARABLE: merged spatial steps S_U | T_P per lifting pair (Sec. 3).
  * SEPARABLE: S_U^V | S_U^H | T_P^V | T_P^H per lifting pair (Sec. 2). */
-typedef enum { DWT2_NONSEPARABLE = 0, DWT2_SEPARABLE = 1 } dwt2_scheme;
+/* Lifting scheme. NONSEPARABLE: the spatial steps T_P and S_U of Sec. 3 (two
+ * steps per lifting pair). SEPARABLE: the horizontal and vertical steps of
+ * Sec. 2 (four per pair). Both move horizontal neighbours between lanes of a
+ * wavefront (no barrier) and vertical ones through LDS with one barrier per
+ * step. The _LDS variants move every neighbour through LDS with a barrier,
+ * as a design whose every step synchronises (Sec. 3's setting); they exist to
+ * measure the barrier count and support FP32 single-image calls with 2-D
+ * tile configurations only (no fused levels, no batches). */
+typedef enum {
+    DWT2_NONSEPARABLE = 0,
+    DWT2_SEPARABLE = 1,
+    DWT2_NONSEPARABLE_LDS = 2,
+    DWT2_SEPARABLE_LDS = 3
+} dwt2_scheme;
 
 /* A 2-D buffer: `height` rows of `width` elements, row starts `pitch`
  * elements apart (pitch >= width), elements of type `dtype`. */

@@ -18,7 +18,9 @@ from . import _lib
 from ._lib import DWT2Error, load  # noqa: F401
 
 WAVELETS = {"cdf97": _lib.CDF97, "cdf53": _lib.CDF53}
-SCHEMES = {"nonseparable": _lib.NONSEPARABLE, "separable": _lib.SEPARABLE}
+SCHEMES = {"nonseparable": _lib.NONSEPARABLE, "separable": _lib.SEPARABLE,
+           # every neighbour exchange through LDS: the barrier-count ablation
+           "nonseparable_lds": _lib.NONSEPARABLE_LDS, "separable_lds": _lib.SEPARABLE_LDS}
 
 
 def _torch():

@@ -15,7 +15,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
 CDF97, CDF53 = 0, 1
 EXT_WHOLE_SAMPLE_SYMMETRIC = 0
 F32, F16, BF16 = 0, 1, 2
-NONSEPARABLE, SEPARABLE = 0, 1
+NONSEPARABLE, SEPARABLE, NONSEPARABLE_LDS, SEPARABLE_LDS = 0, 1, 2, 3
 TILE_TAIL = -2            # tiles[j] of a level that runs in the fused tail launch
 TAIL_MAX = 3
 TAIL_AUTO_PIXELS = 1 << 20

@@ -39,7 +39,13 @@ int hip_fail(hipError_t e) {
 size_t elem_size(int dt) { return dt == DWT2_F32 ? 4 : 2; }
 bool valid_dtype(int dt) { return dt == DWT2_F32 || dt == DWT2_F16 || dt == DWT2_BF16; }
 bool valid_wavelet(int w) { return w == DWT2_CDF97 || w == DWT2_CDF53; }
-bool valid_scheme(int s) { return s == DWT2_NONSEPARABLE || s == DWT2_SEPARABLE; }
+bool valid_scheme(int s) { return s >= DWT2_NONSEPARABLE && s <= DWT2_SEPARABLE_LDS; }
+// The exchange ablation schemes: FP32 level kernels of 2-D tile configurations.
+bool lds_scheme(int s) { return s == DWT2_NONSEPARABLE_LDS || s == DWT2_SEPARABLE_LDS; }
+bool lds_scheme_ok(int tile, int dt0, int dt1, int dt2) {
+    return dt0 == DWT2_F32 && dt1 == DWT2_F32 && dt2 == DWT2_F32 &&
+           (tile < 0 || kTiles[tile].kind == CFG_TILE);
+}
 
 // Byte span [lo, hi) touched by a rows x cols buffer.
 struct Span {
@@ -271,7 +277,9 @@ int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height
     const FwdParams p = fwd_params(in, in_pitch, in_dt, width, height, ll, ll_pitch, ll_dt, hl, lh,
                                    hh, band_pitch, band_dt, wavelet, tile);
     const FwdLauncher f =
-        fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
+        lds_scheme(scheme)
+            ? kFwdLds[wavelet][scheme - DWT2_NONSEPARABLE_LDS][tile]
+            : fwd_table(band_dt)[wavelet][scheme][in_dt == DWT2_F32][ll_dt == DWT2_F32][tile];
     const hipError_t e = f(p, stream);
     return e == hipSuccess ? DWT2_OK : hip_fail(e);
 }
@@ -284,7 +292,9 @@ int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const
     const InvParams p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, band_pitch, band_dt, out,
                                    out_pitch, out_dt, width, height, wavelet, tile);
     const InvLauncher f =
-        inv_table(band_dt)[wavelet][scheme][ll_dt == DWT2_F32][out_dt == DWT2_F32][tile];
+        lds_scheme(scheme)
+            ? kInvLds[wavelet][scheme - DWT2_NONSEPARABLE_LDS][tile]
+            : inv_table(band_dt)[wavelet][scheme][ll_dt == DWT2_F32][out_dt == DWT2_F32][tile];
     const hipError_t e = f(p, stream);
     return e == hipSuccess ? DWT2_OK : hip_fail(e);
 }
@@ -301,6 +311,7 @@ int check_level_args(const void *a, int64_t a_pitch, int a_dt, int32_t width, in
         !valid_wavelet(wavelet) || !valid_scheme(scheme))
         return DWT2_ERR_UNSUPPORTED;
     if (tile >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+    if (lds_scheme(scheme) && !lds_scheme_ok(tile, a_dt, ll_dt, band_dt)) return DWT2_ERR_UNSUPPORTED;
     // The full-resolution and LL buffers are either FP32 or the band type.
     if ((a_dt != band_dt && a_dt != DWT2_F32) || (ll_dt != band_dt && ll_dt != DWT2_F32))
         return DWT2_ERR_INVALID_ARG;
@@ -335,6 +346,12 @@ int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_de
         for (int j = 0; j < levels; ++j)
             if (tiles[j] < DWT2_TILE_TAIL || tiles[j] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
         if (tail_start(W, H, levels, tiles) < 0) return DWT2_ERR_UNSUPPORTED;
+    }
+    if (lds_scheme(scheme)) {   // no fused tail; FP32 2-D tiles only
+        if (xd->dtype != DWT2_F32) return DWT2_ERR_UNSUPPORTED;
+        for (int j = 0; tiles && j < levels; ++j)
+            if (tiles[j] == DWT2_TILE_TAIL || !lds_scheme_ok(tiles[j], DWT2_F32, DWT2_F32, DWT2_F32))
+                return DWT2_ERR_UNSUPPORTED;
     }
     const Span sx = span_of(x, H, W, xd->pitch, xd->dtype);
     const Span sy = span_of(y, H, W, yd->pitch, yd->dtype);
@@ -486,7 +503,7 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2
                               : nullptr};
     char *cbase = static_cast<char *>(coef);
     const int64_t cp = coef_d->pitch;
-    const int k = tail_start(W, H, levels, tiles);
+    const int k = lds_scheme(scheme) ? levels + 1 : tail_start(W, H, levels, tiles);
     FwdTail tail;
     for (int j = 1; j <= levels; ++j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
@@ -549,7 +566,7 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
                               : nullptr};
     const char *cbase = static_cast<const char *>(coef);
     const int64_t cp = coef_d->pitch;
-    const int k = tail_start(W, H, levels, tiles);
+    const int k = lds_scheme(scheme) ? levels + 1 : tail_start(W, H, levels, tiles);
     InvTail tail;
     for (int j = levels; j >= 1; --j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
@@ -612,7 +629,7 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
                        int32_t levels, int32_t boundary, int32_t scheme,
                        const int32_t *class_tiles, void *stream) {
     if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
-    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) ||
+    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
         boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
@@ -670,7 +687,7 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
                        int32_t levels, int32_t boundary, int32_t scheme,
                        const int32_t *class_tiles, void *stream) {
     if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
-    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) ||
+    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
         boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
@@ -740,7 +757,8 @@ template <bool INV>
 int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t scheme,
                 const int32_t *class_tiles, void *stream) {
     if (n < 0 || (n > 0 && !jobs)) return DWT2_ERR_INVALID_ARG;
-    if (!valid_wavelet(wavelet) || !valid_scheme(scheme)) return DWT2_ERR_UNSUPPORTED;
+    if (!valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme))
+        return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
         ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];

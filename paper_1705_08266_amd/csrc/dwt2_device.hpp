@@ -21,7 +21,10 @@
 namespace dwt2 {
 
 enum : int { CDF97 = 0, CDF53 = 1 };
-enum : int { NONSEP = 0, SEP = 1 };
+// NONSEP_LDS and SEP_LDS are the same schemes with every neighbour exchange
+// going through LDS and a workgroup barrier, horizontal ones included (the
+// paper's local-memory design), instead of DPP lane shifts.
+enum : int { NONSEP = 0, SEP = 1, NONSEP_LDS = 2, SEP_LDS = 3 };
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 
 // ---- lifting constants ------------------------------------------------------
@@ -468,7 +471,260 @@ __device__ __forceinline__ void sep_update_v(Quads<ROWS, QPL> &q, Exchange<ROWS,
     }
 }
 
+// ---- every exchange through LDS (ablation of the DPP lane shifts) ------------
+// Per-row edge values of each lane, double-buffered like the mailbox; one
+// exchange publishes, passes one workgroup barrier and reads.
+template <int ROWS, int WAVES>
+struct HBox {
+    float v[2][WAVES][2][ROWS][64];
+};
+
+template <int ROWS, int QPL, int WAVES>
+struct LdsExchange {
+    Mailbox<QPL, WAVES> *box;
+    HBox<ROWS, WAVES> *hb;
+    int wave, lane, buf;
+};
+
+// T_P with the right neighbours (a, c of the next lane's first quad, and the
+// row below) and the lower row read from LDS after one barrier.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void nonsep_predict_lds(Quads<ROWS, QPL> &q,
+                                                   LdsExchange<ROWS, QPL, WAVES> &x, float p) {
+    const float pp = p * p;
+    const int b = x.buf, w = x.wave, l = x.lane;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        x.hb->v[b][w][0][r][l] = q.a[r][0];
+        x.hb->v[b][w][1][r][l] = q.c[r][0];
+    }
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        x.box->v[b][w][0][i][l] = q.a[0][i];
+        x.box->v[b][w][1][i][l] = q.b[0][i];
+    }
+    __syncthreads();
+    const int src = (w + 1 < WAVES) ? w + 1 : w;
+    const int rl = l < 63 ? l + 1 : l;      // the window's last lane reads itself
+    float na[QPL], nb[QPL];
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        na[i] = x.box->v[b][src][0][i][l];
+        nb[i] = x.box->v[b][src][1][i][l];
+    }
+    float aR[ROWS], cR[ROWS], adR[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        aR[r] = x.hb->v[b][w][0][r][rl];
+        cR[r] = x.hb->v[b][w][1][r][rl];
+        adR[r] = (r + 1 < ROWS) ? x.hb->v[b][w][0][(r + 1 < ROWS) ? r + 1 : r][rl]
+                                : x.box->v[b][src][0][0][rl];
+    }
+    x.buf ^= 1;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        float ad[QPL], bd[QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            ad[i] = (r + 1 < ROWS) ? q.a[(r + 1 < ROWS) ? r + 1 : r][i] : na[i];
+            bd[i] = (r + 1 < ROWS) ? q.b[(r + 1 < ROWS) ? r + 1 : r][i] : nb[i];
+        }
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float ar = (i + 1 < QPL) ? q.a[r][(i + 1 < QPL) ? i + 1 : i] : aR[r];
+            const float cr = (i + 1 < QPL) ? q.c[r][(i + 1 < QPL) ? i + 1 : i] : cR[r];
+            const float adr = (i + 1 < QPL) ? ad[(i + 1 < QPL) ? i + 1 : i] : adR[r];
+            const float a = q.a[r][i];
+            float bv = fmaf(p, ar, q.b[r][i]);
+            float c = fmaf(p, ad[i], q.c[r][i]);
+            float d = fmaf(p, cr, q.d[r][i]);
+            d = fmaf(p, bd[i], d);
+            d = fmaf(pp, adr, d);
+            bv = fmaf(p, a, bv);    // T^H_{P0}
+            d = fmaf(p, c, d);
+            c = fmaf(p, a, c);      // T^V_{P0}
+            d = fmaf(p, bv, d);
+            q.b[r][i] = bv; q.c[r][i] = c; q.d[r][i] = d;
+        }
+    }
+}
+
+// S_U with the left neighbours (b, d of the previous lane's last quad, and the
+// row above) and the upper row read from LDS after one barrier.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void nonsep_update_lds(Quads<ROWS, QPL> &q,
+                                                  LdsExchange<ROWS, QPL, WAVES> &x, float u) {
+    const float uu = u * u;
+    const int b = x.buf, w = x.wave, l = x.lane;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        x.hb->v[b][w][0][r][l] = q.b[r][QPL - 1];
+        x.hb->v[b][w][1][r][l] = q.d[r][QPL - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        x.box->v[b][w][0][i][l] = q.c[ROWS - 1][i];
+        x.box->v[b][w][1][i][l] = q.d[ROWS - 1][i];
+    }
+    __syncthreads();
+    const int src = (w > 0) ? w - 1 : w;
+    const int ll = l > 0 ? l - 1 : l;       // the window's first lane reads itself
+    float pc[QPL], pd[QPL];
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        pc[i] = x.box->v[b][src][0][i][l];
+        pd[i] = x.box->v[b][src][1][i][l];
+    }
+    float bL[ROWS], dL[ROWS], duL[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        bL[r] = x.hb->v[b][w][0][r][ll];
+        dL[r] = x.hb->v[b][w][1][r][ll];
+        duL[r] = (r > 0) ? x.hb->v[b][w][1][(r > 0) ? r - 1 : r][ll]
+                         : x.box->v[b][src][1][QPL - 1][ll];
+    }
+    x.buf ^= 1;
+#pragma unroll
+    for (int r = ROWS - 1; r >= 0; --r) {
+        float cu[QPL], du[QPL];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            cu[i] = (r > 0) ? q.c[(r > 0) ? r - 1 : r][i] : pc[i];
+            du[i] = (r > 0) ? q.d[(r > 0) ? r - 1 : r][i] : pd[i];
+        }
+#pragma unroll
+        for (int i = QPL - 1; i >= 0; --i) {
+            const float bl = (i > 0) ? q.b[r][(i > 0) ? i - 1 : i] : bL[r];
+            const float dl = (i > 0) ? q.d[r][(i > 0) ? i - 1 : i] : dL[r];
+            const float dul = (i > 0) ? du[(i > 0) ? i - 1 : i] : duL[r];
+            const float d = q.d[r][i];
+            float a = fmaf(u, bl, q.a[r][i]);
+            a = fmaf(u, cu[i], a);
+            a = fmaf(uu, dul, a);
+            float bv = fmaf(u, du[i], q.b[r][i]);
+            float c = fmaf(u, dl, q.c[r][i]);
+            a = fmaf(u, bv, a);     // S^H_{U0}
+            c = fmaf(u, d, c);
+            a = fmaf(u, c, a);      // S^V_{U0}
+            bv = fmaf(u, d, bv);
+            q.a[r][i] = a; q.b[r][i] = bv; q.c[r][i] = c;
+        }
+    }
+}
+
+// T^H_P through LDS: one barrier.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void sep_predict_h_lds(Quads<ROWS, QPL> &q,
+                                                  LdsExchange<ROWS, QPL, WAVES> &x, float p) {
+    const int b = x.buf, w = x.wave, l = x.lane;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        x.hb->v[b][w][0][r][l] = q.a[r][0];
+        x.hb->v[b][w][1][r][l] = q.c[r][0];
+    }
+    __syncthreads();
+    const int rl = l < 63 ? l + 1 : l;
+    float aR[ROWS], cR[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        aR[r] = x.hb->v[b][w][0][r][rl];
+        cR[r] = x.hb->v[b][w][1][r][rl];
+    }
+    x.buf ^= 1;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float ar = (i + 1 < QPL) ? q.a[r][(i + 1 < QPL) ? i + 1 : i] : aR[r];
+            const float cr = (i + 1 < QPL) ? q.c[r][(i + 1 < QPL) ? i + 1 : i] : cR[r];
+            q.b[r][i] = fmaf(p, ar, fmaf(p, q.a[r][i], q.b[r][i]));
+            q.d[r][i] = fmaf(p, cr, fmaf(p, q.c[r][i], q.d[r][i]));
+        }
+    }
+}
+
+// S^H_U through LDS: one barrier.
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void sep_update_h_lds(Quads<ROWS, QPL> &q,
+                                                 LdsExchange<ROWS, QPL, WAVES> &x, float u) {
+    const int b = x.buf, w = x.wave, l = x.lane;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        x.hb->v[b][w][0][r][l] = q.b[r][QPL - 1];
+        x.hb->v[b][w][1][r][l] = q.d[r][QPL - 1];
+    }
+    __syncthreads();
+    const int ll = l > 0 ? l - 1 : l;
+    float bL[ROWS], dL[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        bL[r] = x.hb->v[b][w][0][r][ll];
+        dL[r] = x.hb->v[b][w][1][r][ll];
+    }
+    x.buf ^= 1;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const float bl = (i > 0) ? q.b[r][(i > 0) ? i - 1 : i] : bL[r];
+            const float dl = (i > 0) ? q.d[r][(i > 0) ? i - 1 : i] : dL[r];
+            q.a[r][i] = fmaf(u, bl, fmaf(u, q.b[r][i], q.a[r][i]));
+            q.c[r][i] = fmaf(u, dl, fmaf(u, q.d[r][i], q.c[r][i]));
+        }
+    }
+}
+
+// The vertical separable steps on the LDS exchange's mailbox (same parity).
+template <int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ Exchange<ROWS, QPL, WAVES> as_exchange(LdsExchange<ROWS, QPL, WAVES> &x) {
+    return Exchange<ROWS, QPL, WAVES>{x.box, x.wave, x.lane, x.buf};
+}
+
 // ---- whole lifting sequences --------------------------------------------------
+template <int WV, int SCH, int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void lift_forward(Quads<ROWS, QPL> &q, LdsExchange<ROWS, QPL, WAVES> &x) {
+    using L = Wavelet<WV>;
+#pragma unroll
+    for (int k = 0; k < L::NPAIRS; ++k) {
+        const float p = (float)L::p(k), u = (float)L::u(k);
+        if constexpr (SCH == NONSEP_LDS) {
+            nonsep_predict_lds(q, x, p);
+            nonsep_update_lds(q, x, u);
+        } else {
+            sep_predict_h_lds(q, x, p);
+            Exchange<ROWS, QPL, WAVES> v = as_exchange(x);
+            sep_predict_v(q, v, p);
+            x.buf = v.buf;
+            sep_update_h_lds(q, x, u);
+            v = as_exchange(x);
+            sep_update_v(q, v, u);
+            x.buf = v.buf;
+        }
+    }
+}
+
+template <int WV, int SCH, int ROWS, int QPL, int WAVES>
+__device__ __forceinline__ void lift_inverse(Quads<ROWS, QPL> &q, LdsExchange<ROWS, QPL, WAVES> &x) {
+    using L = Wavelet<WV>;
+#pragma unroll
+    for (int k = L::NPAIRS - 1; k >= 0; --k) {
+        const float p = -(float)L::p(k), u = -(float)L::u(k);
+        if constexpr (SCH == NONSEP_LDS) {
+            nonsep_update_lds(q, x, u);
+            nonsep_predict_lds(q, x, p);
+        } else {
+            Exchange<ROWS, QPL, WAVES> v = as_exchange(x);
+            sep_update_v(q, v, u);
+            x.buf = v.buf;
+            sep_update_h_lds(q, x, u);
+            v = as_exchange(x);
+            sep_predict_v(q, v, p);
+            x.buf = v.buf;
+            sep_predict_h_lds(q, x, p);
+        }
+    }
+}
+
 template <int WV, int SCH, int ROWS, int QPL, int WAVES>
 __device__ __forceinline__ void lift_forward(Quads<ROWS, QPL> &q, Exchange<ROWS, QPL, WAVES> &x) {
     using L = Wavelet<WV>;

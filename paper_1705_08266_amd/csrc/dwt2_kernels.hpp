@@ -262,10 +262,16 @@ template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename 
 __device__ __forceinline__ void fwd_tile(const FwdParams &prm, int t, Mailbox<QPL, WAVES> &box,
                                          int lane, int wave) {
     using G = TileGeom<WV, QPL, ROWS, WAVES>;
-    Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
     Quads<ROWS, QPL> q;
     fwd_load<QPL, ROWS, G, TIN>(q, prm, t, lane, wave);
-    lift_forward<WV, SCH>(q, x);
+    if constexpr (SCH == NONSEP_LDS || SCH == SEP_LDS) {
+        __shared__ HBox<ROWS, WAVES> hb;
+        LdsExchange<ROWS, QPL, WAVES> x{&box, &hb, wave, lane, 0};
+        lift_forward<WV, SCH>(q, x);
+    } else {
+        Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
+        lift_forward<WV, SCH>(q, x);
+    }
     fwd_store<WV, QPL, ROWS, WAVES, G, TLL, TB>(q, prm, t, lane, wave);
 }
 
@@ -396,7 +402,6 @@ __device__ __forceinline__ void inv_tile(const InvParams &prm, int t, Mailbox<QP
     using L = Wavelet<WV>;
     const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
     const float uHH = (float)(1.0 / (L::ZH * L::ZH));
-    Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
     Quads<ROWS, QPL> q;
     inv_load<QPL, ROWS, G, TLL, TB>(q, prm, t, lane, wave);
 #pragma unroll
@@ -406,7 +411,14 @@ __device__ __forceinline__ void inv_tile(const InvParams &prm, int t, Mailbox<QP
             q.a[r][i] *= uLL; q.b[r][i] *= uHL; q.c[r][i] *= uHL; q.d[r][i] *= uHH;
         }
     }
-    lift_inverse<WV, SCH>(q, x);
+    if constexpr (SCH == NONSEP_LDS || SCH == SEP_LDS) {
+        __shared__ HBox<ROWS, WAVES> hb;
+        LdsExchange<ROWS, QPL, WAVES> x{&box, &hb, wave, lane, 0};
+        lift_inverse<WV, SCH>(q, x);
+    } else {
+        Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
+        lift_inverse<WV, SCH>(q, x);
+    }
     inv_store<QPL, ROWS, WAVES, G, TOUT>(q, prm, t, lane, wave);
 }
 

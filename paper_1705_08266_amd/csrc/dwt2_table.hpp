@@ -239,6 +239,46 @@ constexpr InvTailTable make_inv_tail_table() {
              {inv_tail_depths<T, CDF53, NONSEP>(), inv_tail_depths<T, CDF53, SEP>()}}};
 }
 
+// The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels of the 2-D
+// tile configurations only, index [wavelet][scheme - NONSEP_LDS][config].
+using FwdLdsTable = std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>;
+using InvLdsTable = std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>;
+
+template <int WV, int SCH, int T>
+hipError_t launch_fwd_lds(const FwdParams &p, hipStream_t s) {
+    if constexpr (kTiles[T].kind != CFG_TILE) {
+        return hipErrorInvalidValue;
+    } else {
+        return launch_fwd<WV, SCH, T, float, float, float>(p, s);
+    }
+}
+template <int WV, int SCH, int T>
+hipError_t launch_inv_lds(const InvParams &p, hipStream_t s) {
+    if constexpr (kTiles[T].kind != CFG_TILE) {
+        return hipErrorInvalidValue;
+    } else {
+        return launch_inv<WV, SCH, T, float, float, float>(p, s);
+    }
+}
+template <int WV, int SCH, int... I>
+constexpr std::array<FwdLauncher, kNumTiles> fwd_lds_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_fwd_lds<WV, SCH, I>...};
+}
+template <int WV, int SCH, int... I>
+constexpr std::array<InvLauncher, kNumTiles> inv_lds_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_inv_lds<WV, SCH, I>...};
+}
+inline constexpr FwdLdsTable make_fwd_lds_table() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{fwd_lds_tiles<CDF97, NONSEP_LDS>(S{}), fwd_lds_tiles<CDF97, SEP_LDS>(S{})},
+             {fwd_lds_tiles<CDF53, NONSEP_LDS>(S{}), fwd_lds_tiles<CDF53, SEP_LDS>(S{})}}};
+}
+inline constexpr InvLdsTable make_inv_lds_table() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{inv_lds_tiles<CDF97, NONSEP_LDS>(S{}), inv_lds_tiles<CDF97, SEP_LDS>(S{})},
+             {inv_lds_tiles<CDF53, NONSEP_LDS>(S{}), inv_lds_tiles<CDF53, SEP_LDS>(S{})}}};
+}
+
 // Defined in one translation unit per storage type and direction.
 extern FwdTable kFwdF32, kFwdF16, kFwdBF16;
 extern InvTable kInvF32, kInvF16, kInvBF16;
@@ -246,5 +286,7 @@ extern FwdBatchTable kFwdBatchF32, kFwdBatchF16, kFwdBatchBF16;
 extern InvBatchTable kInvBatchF32, kInvBatchF16, kInvBatchBF16;
 extern FwdTailTable kFwdTailF32, kFwdTailF16, kFwdTailBF16;
 extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
+extern FwdLdsTable kFwdLds;
+extern InvLdsTable kInvLds;
 
 }  // namespace dwt2

@@ -136,6 +136,24 @@ def test_fused_tail_tile_ids():
     assert _lib.load().dwt2_fused_levels(64, 64, 7) == _lib.ERR_INVALID_ARG
 
 
+def test_exchange_ablation_scheme_limits():
+    """The LDS-exchange schemes take FP32 and 2-D tile configurations only,
+    and no fused levels or batches."""
+    U, W = _lib.ERR_UNSUPPORTED, _lib.ERR_WORKSPACE
+    for sch in (_lib.NONSEPARABLE_LDS, _lib.SEPARABLE_LDS):
+        assert _fwd(levels=2, scheme=sch) == W                    # accepted up to the workspace
+        assert _fwd(sd=_lib.Desc(64, 64, 64, _lib.F16), dd=_lib.Desc(64, 64, 64, _lib.F16),
+                    scheme=sch) == U
+        assert _fwd(levels=2, scheme=sch, tiles=(ctypes.c_int32 * 2)(_lib.TILE_TAIL,
+                                                                      _lib.TILE_TAIL)) == U
+        stream_cfg = [c[0] for c in __import__("paper_1705_08266_amd").tile_configs() if c[1] == 1][0]
+        assert _fwd(scheme=sch, tiles=(ctypes.c_int32 * 1)(stream_cfg)) == U
+        lib = _lib.load()
+        assert lib.dwt2_forward_batch(None, 0, _lib.F32, 0, 1, 0, sch, None, None) == U
+        assert lib.dwt2_forward_level_batch(None, 0, 0, sch, None, None) == U
+    assert _fwd(scheme=4) == U
+
+
 def test_inverse_argument_errors():
     lib = _lib.load()
     d = _lib.Desc(32, 32, 32, _lib.F32)
