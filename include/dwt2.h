@@ -31,9 +31,12 @@
  * Memory and threading
  *   - All buffer pointers are DEVICE pointers on the current HIP device.
  *   - The caller owns every buffer. The library allocates and frees no device
- *     memory, keeps no global mutable state except a thread-local last HIP
- *     error, and never synchronises: every call enqueues work on `stream`
- *     (a hipStream_t; NULL = the default stream) and returns.
+ *     memory (the batch entry points use host-side scratch for their launch
+ *     descriptors), keeps no global mutable state except a thread-local last
+ *     HIP error and per-process caches of device properties (compute-unit
+ *     and occupancy counts), and never synchronises: every call enqueues
+ *     work on `stream` (a hipStream_t; NULL = the default stream) and
+ *     returns.
  *   - Argument errors are detected before anything is enqueued. Faults during
  *     execution surface at the caller's next synchronisation of `stream`.
  *   - Calls on different streams that use disjoint buffers may overlap.

@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "dwt2.h"
 #include "dwt2_table.hpp"
@@ -644,9 +645,11 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
     }
     const hipStream_t s = (hipStream_t)stream;
     const size_t es = elem_size(dtype);
-    FwdParams *params = new FwdParams[n > 0 ? n : 1];
-    int *cls = new int[n > 0 ? n : 1];
-    int *tiles = new int[n > 0 ? n : 1];
+    std::vector<FwdParams> params_v(n > 0 ? n : 1);
+    std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
+    FwdParams *params = params_v.data();
+    int *cls = cls_v.data();
+    int *tiles = tiles_v.data();
     int st = DWT2_OK;
     for (int j = 1; j <= levels && st == DWT2_OK; ++j) {
         for (int i = 0; i < n; ++i) {
@@ -677,9 +680,6 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
             return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
         });
     }
-    delete[] params;
-    delete[] cls;
-    delete[] tiles;
     return st;
 }
 
@@ -702,9 +702,11 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
     }
     const hipStream_t s = (hipStream_t)stream;
     const size_t es = elem_size(dtype);
-    InvParams *params = new InvParams[n > 0 ? n : 1];
-    int *cls = new int[n > 0 ? n : 1];
-    int *tiles = new int[n > 0 ? n : 1];
+    std::vector<InvParams> params_v(n > 0 ? n : 1);
+    std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
+    InvParams *params = params_v.data();
+    int *cls = cls_v.data();
+    int *tiles = tiles_v.data();
     int st = DWT2_OK;
     for (int j = levels; j >= 1 && st == DWT2_OK; --j) {
         for (int i = 0; i < n; ++i) {
@@ -735,9 +737,6 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
             return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
         });
     }
-    delete[] params;
-    delete[] cls;
-    delete[] tiles;
     return st;
 }
 
@@ -773,8 +772,8 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
         if (st) return st;
     }
     const hipStream_t s = (hipStream_t)stream;
-    JobKey *keys = new JobKey[n > 0 ? n : 1];
-    bool *done = new bool[n > 0 ? n : 1];
+    std::vector<JobKey> keys(n > 0 ? n : 1);
+    std::vector<char> done(n > 0 ? n : 1);
     for (int i = 0; i < n; ++i) {
         keys[i] = {size_class(jobs[i].width, jobs[i].height), jobs[i].full_dtype, jobs[i].ll_dtype,
                    jobs[i].band_dtype};
@@ -818,8 +817,6 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
             }
         }
     }
-    delete[] keys;
-    delete[] done;
     return st;
 }
 

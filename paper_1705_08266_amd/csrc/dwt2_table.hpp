@@ -93,9 +93,12 @@ hipError_t launch_fwd_batch(const FwdBatch &b, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         const auto k = fwd_batch_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>;
-        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
         const int total = b.tile_start[b.n];
-        const int grid = kBatchPersistent ? (total < resident ? total : resident) : total;
+        int grid = total;
+        if constexpr (kBatchPersistent) {
+            static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+            grid = total < resident ? total : resident;
+        }
         if (grid <= 0) return hipSuccess;
         hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
         return hipGetLastError();
@@ -109,9 +112,12 @@ hipError_t launch_inv_batch(const InvBatch &b, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         const auto k = inv_batch_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>;
-        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
         const int total = b.tile_start[b.n];
-        const int grid = kBatchPersistent ? (total < resident ? total : resident) : total;
+        int grid = total;
+        if constexpr (kBatchPersistent) {
+            static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+            grid = total < resident ? total : resident;
+        }
         if (grid <= 0) return hipSuccess;
         hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
         return hipGetLastError();

@@ -56,6 +56,25 @@ def test_results_identical_alone_and_in_the_mix():
         assert torch.equal(solo.output, out.output), req
 
 
+@pytest.mark.parametrize("dtype,tdt", [("f32", torch.float32), ("bf16", torch.bfloat16)])
+def test_other_storage_types_identical_alone_and_in_the_mix(dtype, tdt):
+    reqs, inputs, images = _workload(16, seed=31, hi=768, dtype=tdt)
+    srv = sv.Server(dtype=dtype, max_active=6)
+    res = srv.run(reqs, inputs, keep_outputs=True, realtime=False)
+    torch.cuda.synchronize()
+    by_id = {r.rid: r for r in reqs}
+    for out in res:
+        req = by_id[out.rid]
+        assert out.output.dtype == tdt
+        assert torch.equal(_alone(req, inputs[req.rid]), out.output), req
+
+
+def test_server_rejects_inputs_of_another_storage_type():
+    reqs, inputs, images = _workload(2, seed=3, hi=256)
+    with pytest.raises(ValueError):
+        sv.Server(dtype="f32").run(reqs, inputs)
+
+
 def test_mix_within_fp16_bound_of_the_oracle():
     reqs, inputs, images = _workload(12, seed=5, hi=512)
     res = sv.Server().run(reqs, inputs, keep_outputs=True, realtime=False)
