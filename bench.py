@@ -11,7 +11,14 @@ from HBM rather than from the cache.
 Prints one JSON line with the throughput in Gpixel/s (original-image pixels
 per second of forward+inverse), the roofline of the dominant kernel
 (level-1 launch, HBM-bound), the separable-lifting kernel measured the same
-way, and the FP64 oracle timed on the host cores.
+way, both schemes with every neighbour exchange through LDS (the barrier
+ablation), the serving half of the metric (p50/p99 latency of the mixed
+FP16 request stream at 0.8 of its saturation rate), and the FP64 oracle
+timed on the host cores.
+
+Other workloads: --workload batch (256 uneven images, batched launches in a
+graph) and --workload serve (the full serving sweep); --size, --levels,
+--wavelet and --dtype select the other image configurations.
 """
 from __future__ import annotations
 
@@ -29,7 +36,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = ("Gpixel/s fwd+inv CDF 9/7 DWT at 4096², 5 levels (% HBM peak); "
           "serving p50/p99")
-KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp", "dwt2_table.hpp", "dwt2_api.hip")
+# Traffic counters are valid for the kernel code they were taken with (these
+# sources) and the tile geometry named in their key.
+KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp")
 
 
 def kernel_source_sha() -> str:
@@ -326,14 +335,30 @@ def run_serve_workload(args):
     inverse 50/50, FP16 storage with FP32 intermediates, 64 GB admission
     budget. First the saturation throughput (every request offered at time
     zero), then p50/p99 latency at 0.5, 0.8 and 0.95 of it."""
+    n, px, sat, sweep = serve_measure(args, args.requests, args.dtype, (0.5, 0.8, 0.95))
+    print(json.dumps(dict(
+        metric="Gpixel/s serving throughput, continuous batching of mixed requests",
+        value=sat["gpixel_per_s"], unit="Gpixel/s", n_gpus=1, steps=n, warmup=n,
+        ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=args.dtype, data="synthetic",
+        config=dict(workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples "
+                             f"of 64), levels 1..6, forward/inverse 50/50, {args.dtype} storage "
+                             f"with FP32 intermediates, 64 GB admission budget",
+                    requests=n, pixels=px),
+        saturation=sat, latency_sweep=sweep)), flush=True)
+
+
+def serve_measure(args, n, dtype, fractions):
+    """Serving runs on one seeded request set: saturation (all offered at
+    time zero) and Poisson arrivals at the given fractions of it. Returns
+    (requests, pixels, saturation, {fraction: result})."""
     import numpy as np
     import torch
     import synthetic
     import paper_1705_08266_amd as dwt
     from paper_1705_08266_amd import serving as sv
 
-    n = args.requests
-    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
     trace = synthetic.request_stream(n, 1.0, seed=synthetic.SEED_BASE + 5)
     reqs = [sv.Request(r.rid, 0.0, r.side, r.side, r.levels, r.inverse) for r in trace]
     inputs = {}
@@ -342,12 +367,12 @@ def run_serve_workload(args):
         inputs[r.rid] = dwt.forward(x, args.wavelet, r.levels) if r.inverse else x
     torch.cuda.synchronize()
     px = sum(r.width * r.height for r in reqs)
-    print(f"[bench] serve: {n} requests, {px / 1e6:.0f} Mpx, {args.dtype}", file=sys.stderr,
+    print(f"[bench] serve: {n} requests, {px / 1e6:.0f} Mpx, {dtype}", file=sys.stderr,
           flush=True)
 
     def serve(rate):
         srv = sv.Server(budget_bytes=64 << 30, wavelet=args.wavelet, scheme=args.scheme,
-                        dtype=args.dtype)
+                        dtype=dtype)
         if rate is None:
             res = srv.run(reqs, inputs, realtime=False)
         else:
@@ -370,19 +395,12 @@ def run_serve_workload(args):
     serve(None)                                  # warm-up: allocator, kernel loads
     sat = serve(None)
     sweep = {}
-    for f in (0.5, 0.8, 0.95):
+    for f in fractions:
         sweep[str(f)] = dict(offered_per_s=round(f * sat["requests_per_s"], 1),
                              **serve(f * sat["requests_per_s"]))
-    print(json.dumps(dict(
-        metric="Gpixel/s serving throughput, continuous batching of mixed requests",
-        value=sat["gpixel_per_s"], unit="Gpixel/s", n_gpus=1, steps=n, warmup=n,
-        ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype=args.dtype, data="synthetic",
-        config=dict(workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples "
-                             f"of 64), levels 1..6, forward/inverse 50/50, {args.dtype} storage "
-                             f"with FP32 intermediates, 64 GB admission budget",
-                    requests=n, pixels=px),
-        saturation=sat, latency_sweep=sweep)), flush=True)
+    del inputs
+    torch.cuda.empty_cache()
+    return n, px, sat, sweep
 
 
 def main():
@@ -401,6 +419,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-separable", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving latency measurement of the default workload")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the schemes whose every neighbour exchange goes through LDS")
     ap.add_argument("--eager", action="store_true",
@@ -482,7 +502,10 @@ def main():
     all_fused = 1 in main_run["fused_levels"]
     dom_bytes = sum(lb) if all_fused else lb[0]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    kernel_key = f"{dom}_level1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
+    import paper_1705_08266_amd as dwt
+    _, _, qpl, rows, waves, _, _ = dwt.tile_configs(args.wavelet)[dwt.default_tile(W, H)]
+    kernel_key = (f"{dom}_level1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
+                  f"_q{qpl}r{rows}w{waves}")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if all_fused else load_traffic(kernel_key),
@@ -530,6 +553,19 @@ def main():
                                      inverse=round(r["inv_level_ms"][0], 5)),
                       barriers_per_lifting_pair=2 if sch.startswith("nonsep") else 4)
             for sch, r in ablation.items()}
+
+    if not args.no_serving and (W, H, L) == (4096, 4096, 5) and args.dtype == "f32":
+        # the serving half of the metric: p50/p99 latency of the serving
+        # workload (FP16 storage) at 0.8 of its measured saturation rate
+        n, px, sat, sweep = serve_measure(args, 200, "f16", (0.8,))
+        at = sweep["0.8"]
+        result["serving"] = dict(
+            workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples of 64), "
+                     f"levels 1..6, forward/inverse 50/50, f16 storage, 64 GB admission budget",
+            saturation_gpixel_per_s=sat["gpixel_per_s"],
+            saturation_requests_per_s=sat["requests_per_s"],
+            offered_per_s=at["offered_per_s"], gpixel_per_s=at["gpixel_per_s"],
+            p50_ms=at["p50_ms"], p99_ms=at["p99_ms"])
 
     x_stored = main_run["stored"].astype(np.float64)
     scale = float(np.abs(x_stored).max())
