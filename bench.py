@@ -155,6 +155,27 @@ def run_gpu(args, x_np, scheme):
     total_ms = t_start.elapsed_time(t_end)
     replay_matches = bool(torch.equal(sets[0][1], eager_coef) and torch.equal(sets[0][2], eager_rec))
 
+    # The same K steps with consecutive steps (independent buffer sets) on two
+    # streams, so that one chain's launch gaps overlap the other's kernels.
+    concurrent_ms = None
+    if graphs and len(graphs) >= 2:
+        side = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+        for _ in range(2):
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            c0.record(stream)
+            for st in side:
+                st.wait_event(c0)
+            for k in range(K):
+                with torch.cuda.stream(side[k % 2]):
+                    graphs[k % len(graphs)].replay()
+            for st in side:
+                stream.wait_stream(st)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            concurrent_ms = c0.elapsed_time(c1)
+
     # per-level kernel durations: each level's launch repeated back to back,
     # bracketed by events on the launch stream, buffers rotating
     R = 40
@@ -222,6 +243,7 @@ def run_gpu(args, x_np, scheme):
             (fwd_ms if direction == "forward" else inv_ms).append(e0.elapsed_time(e1) / R)
 
     out = dict(total_ms=total_ms, wall_s=wall, fwd_level_ms=fwd_ms, inv_level_ms=inv_ms,
+               concurrent_ms=concurrent_ms,
                fused_levels=list(range(k_tail, L + 1)) if fused else [],
                coef=eager_coef.float().cpu().numpy(), rec=eager_rec.float().cpu().numpy(),
                stored=sets[0][0].float().cpu().numpy(), graph=bool(graphs),
@@ -534,6 +556,10 @@ def main():
         fused_levels=main_run["fused_levels"],
         launch=("one captured HIP graph per buffer set (forward + inverse chain)"
                 if main_run["graph"] else "eager launches"),
+        two_streams=(None if main_run["concurrent_ms"] is None else dict(
+            value=round(W * H / (main_run["concurrent_ms"] / K * 1e-3) / 1e9, 3),
+            ms_per_step=round(main_run["concurrent_ms"] / K, 5),
+            note="the same steps, consecutive ones (independent images) on two streams")),
         graph_replay_matches_eager=main_run["replay_matches_eager"],
     )
     if sep_run is not None:
