@@ -461,9 +461,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the transform of one image is not sharded "
-              "across GPUs in this build (see DESIGN.md for how it would shard). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs a transform on one device and "
+              "does not shard it across GPUs. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
