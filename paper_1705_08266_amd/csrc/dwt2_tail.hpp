@@ -50,6 +50,20 @@ struct InvTail {
     int32_t e[kTailMax];
 };
 
+// Workgroup barriers in one lifting sequence (one per vertical exchange).
+template <int WV>
+constexpr int kLiftBarriers = 2 * Wavelet<WV>::NPAIRS;
+
+// Wavefronts whose rows lie below a level's window skip that level's work
+// but pass the same barriers. Their stale mailbox slots feed only the rows
+// within the lifting radius of the window's lower edge, which are never
+// stored, as at the window edge itself.
+template <int WV>
+__device__ __forceinline__ void idle_through_lifting() {
+#pragma unroll
+    for (int k = 0; k < kLiftBarriers<WV>; ++k) __syncthreads();
+}
+
 struct Region {
     int ox0, ox1, oy0, oy1;   // owned quads (clipped to the level)
     int cx0, cx1, cy0, cy1;   // computed quads: owned plus extension (clipped)
@@ -100,6 +114,13 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
         const Region g = tail_region(bx, by, t.B << (F - 1 - m), t.e[m], prm.nqx, prm.nqy);
         const int qx = g.cx0 - R + lane;          // the lane's quad column
         const int qy0 = g.cy0 - R + wave * ROWS;  // its first quad row
+        const int cw = g.cx1 - g.cx0;
+        if (wave * ROWS >= (g.cy1 - g.cy0) + 2 * R) {   // below this level's window
+            idle_through_lifting<WV>();
+            px0 = g.cx0; py0 = g.cy0; pw = cw; ph = g.cy1 - g.cy0;
+            __syncthreads();
+            continue;
+        }
         Quads<ROWS, QPL> q;
         if (m == 0) {
             fwd_load_at<QPL, ROWS, TIN>(q, prm, qx, qy0);
@@ -120,7 +141,6 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
         Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
         lift_forward<WV, SCH>(q, x);
         const bool last = m == F - 1;
-        const int cw = g.cx1 - g.cx0;
         float *dst = llbuf[m & 1];
         // lanes outside the owned columns store nowhere
         const uint32_t ob = (qx >= g.ox0 && qx < g.ox1) ? (uint32_t)qx * sizeof(TB) : kNoAccess;
@@ -166,6 +186,13 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
         const Region g = tail_region(bx, by, t.B << m, t.e[m], prm.nqx, prm.nqy);
         const int qx = g.cx0 - R + lane;
         const int qy0 = g.cy0 - R + wave * ROWS;
+        const int cw = 2 * (g.cx1 - g.cx0);
+        if (wave * ROWS >= (g.cy1 - g.cy0) + 2 * R) {   // below this level's window
+            idle_through_lifting<WV>();
+            px0 = 2 * g.cx0; py0 = 2 * g.cy0; pw = cw; ph = 2 * (g.cy1 - g.cy0);
+            __syncthreads();
+            continue;
+        }
         Quads<ROWS, QPL> q;
         if (m == 0) {
             inv_load_at<QPL, ROWS, TLL, TB>(q, prm, qx, qy0);
@@ -195,7 +222,6 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
         Exchange<ROWS, QPL, WAVES> x{&box, wave, lane, 0};
         lift_inverse<WV, SCH>(q, x);
         const bool last = m == F - 1;
-        const int cw = 2 * (g.cx1 - g.cx0);
         float *dst = pxbuf[m & 1];
         const uint32_t oo = (qx >= g.ox0 && qx < g.ox1) ? 2u * (uint32_t)qx * sizeof(TOUT)
                                                         : kNoAccess;
