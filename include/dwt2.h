@@ -189,7 +189,9 @@ int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind,
                           int32_t *quads_per_lane, int32_t *rows,
                           int32_t *waves, int32_t *out_x, int32_t *out_y);
 
-/* The tile id the library picks for one level of the given size. */
+/* The tile id the library picks for one level whose full-resolution side
+ * (the forward's input, the inverse's output) is width x height pixels of
+ * `dtype` storage. */
 int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet,
                       int32_t scheme, int32_t dtype);
 

@@ -126,10 +126,13 @@ Plan plan_level(int tile, int wavelet, int nqx, int nqy) {
 
 // Configuration choice for one level: the 128 x 16-quad window held by 8
 // wavefronts of 2 quad rows was the fastest measured configuration from
-// 1024^2 to 4096^2 levels in both directions (more wavefronts with fewer
-// rows each keep more loads in flight per workgroup than 4 of 4 rows).
-int pick_tile(int width, int height, int wavelet) {
-    (void)width; (void)height; (void)wavelet;
+// 1024^2 to 4096^2 levels in both directions with FP32 storage (more
+// wavefronts with fewer rows each keep more loads in flight per workgroup
+// than 4 of 4 rows). With 16-bit storage each lane moves half the bytes per
+// row, and above 2048^2 pixels 4 wavefronts of 4 rows measured faster.
+int pick_tile(int width, int height, int wavelet, int storage) {
+    (void)wavelet;
+    if (storage != DWT2_F32 && (int64_t)width * height > (int64_t)2048 * 2048) return 1;
     return 10;
 }
 
@@ -274,7 +277,7 @@ int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height
               void *ll, int64_t ll_pitch, int ll_dt, void *hl, void *lh, void *hh,
               int64_t band_pitch, int band_dt, int wavelet, int scheme, int tile,
               hipStream_t stream) {
-    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    if (tile < 0) tile = pick_tile(width, height, wavelet, in_dt);
     const FwdParams p = fwd_params(in, in_pitch, in_dt, width, height, ll, ll_pitch, ll_dt, hl, lh,
                                    hh, band_pitch, band_dt, wavelet, tile);
     const FwdLauncher f =
@@ -289,7 +292,7 @@ int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const
               const void *hh, int64_t band_pitch, int band_dt, void *out, int64_t out_pitch,
               int out_dt, int width, int height, int wavelet, int scheme, int tile,
               hipStream_t stream) {
-    if (tile < 0) tile = pick_tile(width, height, wavelet);
+    if (tile < 0) tile = pick_tile(width, height, wavelet, out_dt);
     const InvParams p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, band_pitch, band_dt, out,
                                    out_pitch, out_dt, width, height, wavelet, tile);
     const InvLauncher f =
@@ -459,9 +462,9 @@ int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind, int32_t 
 
 int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet, int32_t scheme,
                       int32_t dtype) {
-    (void)scheme; (void)dtype;
+    (void)scheme;
     if (check_level_dims(width, height) || !valid_wavelet(wavelet)) return DWT2_ERR_INVALID_ARG;
-    return pick_tile(width, height, wavelet);
+    return pick_tile(width, height, wavelet, valid_dtype(dtype) ? dtype : DWT2_F32);
 }
 
 int dwt2_forward_level(const void *in, int64_t in_pitch, int32_t in_dtype, int32_t width,
