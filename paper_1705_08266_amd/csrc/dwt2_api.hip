@@ -227,7 +227,11 @@ int size_class(int width, int height) {
     return 3;
 }
 // Default 2-D tile per size class.
-const int kClassTile[DWT2_SIZE_CLASSES] = {10, 10, 10, 10};
+// Default 2-D tile per size class and storage type (the same choice as
+// pick_tile for a level of that class).
+int class_tile(int cls, int storage) {
+    return (cls == DWT2_SIZE_CLASSES - 1 && storage != DWT2_F32) ? 1 : 10;
+}
 
 int check_level_dims(int32_t width, int32_t height) {
     if (width < 2 || height < 2 || (width & 1) || (height & 1)) return DWT2_ERR_INVALID_ARG;
@@ -638,7 +642,7 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
+        ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
         if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
             return DWT2_ERR_UNSUPPORTED;
     }
@@ -695,7 +699,7 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
+        ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
         if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
             return DWT2_ERR_UNSUPPORTED;
     }
@@ -763,8 +767,9 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        ctile[c] = class_tiles ? class_tiles[c] : kClassTile[c];
-        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
+        ctile[c] = class_tiles ? class_tiles[c] : -1;   // -1: by storage, per group below
+        if (class_tiles &&
+            (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE))
             return DWT2_ERR_UNSUPPORTED;
     }
     for (int i = 0; i < n; ++i) {
@@ -787,7 +792,7 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
     for (int g = 0; g < n && st == DWT2_OK; ++g) {
         if (done[g]) continue;
         const JobKey key = keys[g];
-        const int tile = ctile[key.cls];
+        const int tile = ctile[key.cls] >= 0 ? ctile[key.cls] : class_tile(key.cls, key.full_dt);
         typename std::conditional<INV, InvBatch, FwdBatch>::type b;
         b.n = 0;
         b.tile_start[0] = 0;
