@@ -136,6 +136,12 @@ int pick_tile(int width, int height, int wavelet, int storage) {
     return 10;
 }
 
+// Smallest reconstructed image (bytes) that dwt2_inverse writes with
+// non-temporal stores. Nothing in the transform reads its output again; at
+// this size and above, streaming it past the caches made the final level
+// faster, and smaller images stay cached for whatever consumes them next.
+constexpr int64_t kStreamOutBytes = (int64_t)32 << 20;
+
 const FwdTable &fwd_table(int dt) {
     return dt == DWT2_F32 ? kFwdF32 : dt == DWT2_F16 ? kFwdF16 : kFwdBF16;
 }
@@ -274,6 +280,7 @@ InvParams inv_params(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
     p.vec_out = aligned(out, out_pitch, out_dt, 2 * q);
+    p.stream_out = 0;
     return p;
 }
 
@@ -295,10 +302,11 @@ int fwd_level(const void *in, int64_t in_pitch, int in_dt, int width, int height
 int inv_level(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl, const void *lh,
               const void *hh, int64_t band_pitch, int band_dt, void *out, int64_t out_pitch,
               int out_dt, int width, int height, int wavelet, int scheme, int tile,
-              hipStream_t stream) {
+              hipStream_t stream, bool stream_out = false) {
     if (tile < 0) tile = pick_tile(width, height, wavelet, out_dt);
-    const InvParams p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, band_pitch, band_dt, out,
-                                   out_pitch, out_dt, width, height, wavelet, tile);
+    InvParams p = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, band_pitch, band_dt, out,
+                             out_pitch, out_dt, width, height, wavelet, tile);
+    p.stream_out = stream_out;
     const InvLauncher f =
         lds_scheme(scheme)
             ? kInvLds[wavelet][scheme - DWT2_NONSEPARABLE_LDS][tile]
@@ -616,8 +624,10 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
         }
         const int tile = tiles ? tiles[j - 1] : -1;
         if ((st = record(level_events, 2 * (j - 1), s))) return st;
+        // the reconstructed image is the transform's last write
+        const bool stream_out = j == 1 && (int64_t)W * H * (int64_t)es >= kStreamOutBytes;
         st = inv_level(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out, out_pitch, out_dt, w, h,
-                       wavelet, scheme, tile, s);
+                       wavelet, scheme, tile, s, stream_out);
         if (st) return st;
         if ((st = record(level_events, 2 * (j - 1) + 1, s))) return st;
     }

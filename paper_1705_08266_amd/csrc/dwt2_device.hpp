@@ -114,6 +114,12 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
                                              kRsrcWord3);
 }
 
+// Cache policy of a buffer store (the instruction's cache-policy operand).
+// kStoreStream sets the non-temporal bit: the written lines go out to memory
+// without being kept in the caches for reuse, for output that no later step
+// of the transform reads.
+constexpr int kStoreCached = 0, kStoreStream = 2;
+
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -135,19 +141,19 @@ __device__ __forceinline__ void buf_load_words(rsrc_t r, uint32_t off, uint32_t 
     }
 }
 
-template <int W>
+template <int W, int POLICY = kStoreCached>
 __device__ __forceinline__ void buf_store_words(rsrc_t r, uint32_t off, const uint32_t (&w)[W]) {
     static_assert(W == 1 || W == 2 || W == 4 || W == 8, "access width");
     if constexpr (W == 1) {
-        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)off, 0, POLICY);
     } else if constexpr (W == 2) {
         u32x2 v; v.x = w[0]; v.y = w[1];
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, POLICY);
     } else {
 #pragma unroll
         for (int h = 0; h < W / 4; ++h) {
             u32x4 v; v.x = w[4 * h]; v.y = w[4 * h + 1]; v.z = w[4 * h + 2]; v.w = w[4 * h + 3];
-            __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(off + 16u * h), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(off + 16u * h), 0, POLICY);
         }
     }
 }
@@ -197,7 +203,7 @@ __device__ __forceinline__ void load_vec(rsrc_t r, uint32_t off, float (&out)[N]
     }
 }
 
-template <typename T, int N>
+template <typename T, int N, int POLICY = kStoreCached>
 __device__ __forceinline__ void store_vec(rsrc_t r, uint32_t off, const float (&in)[N]) {
     constexpr int BYTES = N * (int)sizeof(T);
     if constexpr (BYTES == 2) {
@@ -214,7 +220,7 @@ __device__ __forceinline__ void store_vec(rsrc_t r, uint32_t off, const float (&
                 w[e / 2] = bits_of<T>(from_float<T>(in[e])) |
                            (bits_of<T>(from_float<T>(in[e + 1])) << 16);
         }
-        buf_store_words<BYTES / 4>(r, off, w);
+        buf_store_words<BYTES / 4, POLICY>(r, off, w);
     }
 }
 

@@ -36,8 +36,9 @@ struct InvParams {
     int64_t out_pitch;
     int32_t w, h, nqx, nqy;
     int32_t tiles_x, tiles_y;
-    int32_t seg;
-    int32_t vec_ll, vec_band, vec_out;
+    int32_t seg;                         // streaming kernels: output rows per segment
+    uint8_t vec_ll, vec_band, vec_out;   // 1 when vector accesses are aligned
+    uint8_t stream_out;                  // 1: vector output stores are non-temporal
 };
 
 // Geometry of a tile configuration. The horizontal halo is one lane's worth
@@ -381,8 +382,13 @@ __device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvPa
         if (full_x) {
             const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TOUT);
             const uint32_t off = (uint32_t)px0 * (uint32_t)sizeof(TOUT);
-            store_vec<TOUT, 2 * QPL>(make_rsrc(r0, rb), off, e);
-            store_vec<TOUT, 2 * QPL>(make_rsrc(r1, rb), off, o);
+            if (prm.stream_out) {
+                store_vec<TOUT, 2 * QPL, kStoreStream>(make_rsrc(r0, rb), off, e);
+                store_vec<TOUT, 2 * QPL, kStoreStream>(make_rsrc(r1, rb), off, o);
+            } else {
+                store_vec<TOUT, 2 * QPL>(make_rsrc(r0, rb), off, e);
+                store_vec<TOUT, 2 * QPL>(make_rsrc(r1, rb), off, o);
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < 2 * QPL; ++k) {
