@@ -11,11 +11,13 @@ input from HBM rather than from the cache.
 
 Prints one JSON line with the throughput in Gpixel/s (original-image pixels
 per second of forward+inverse), the roofline of the dominant kernel
-(level-1 launch, HBM-bound), the separable-lifting kernel measured the same
-way, both schemes with every neighbour exchange through LDS (the barrier
-ablation), the serving half of the metric (p50/p99 latency of the mixed
-FP16 request stream at 0.8 of its saturation rate), and the FP64 oracle
-timed on the host cores.
+(level-1 launch, HBM-bound; also as a fraction of the runtime's measured
+device-copy bandwidth), the median and p10 / p90 of single steps, the same
+steps with a warm Infinity Cache, the separable-lifting kernel measured the
+same way, both schemes with every neighbour exchange through LDS (the
+barrier ablation), the serving half of the metric (p50/p99 latency of the
+mixed FP16 request stream at 0.8 of its saturation rate), and the FP64
+oracle timed on the host cores (all cores and one).
 
 Other workloads: --workload batch (256 uneven images, batched launches in a
 graph) and --workload serve (the full serving sweep); --size, --levels,
@@ -51,6 +53,7 @@ def kernel_source_sha() -> str:
 
 
 INFINITY_CACHE_BYTES = 256 << 20
+STEP_SAMPLES = 50   # individually timed steps for the median and p10 / p90
 
 
 def buffer_sets(args, W, H) -> int:
@@ -169,6 +172,32 @@ def run_gpu(args, x_np, scheme):
     total_ms = t_start.elapsed_time(t_end)
     replay_matches = bool(torch.equal(sets[0][1], eager_coef) and torch.equal(sets[0][2], eager_rec))
 
+    # Spread of single steps: each replay bracketed by its own events (cold
+    # buffers, rotating as above).
+    step_ms = []
+    if graphs:
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(STEP_SAMPLES)]
+        for k, (a, b) in enumerate(pairs):
+            a.record(stream)
+            graphs[k % len(graphs)].replay()
+            b.record(stream)
+        torch.cuda.synchronize()
+        step_ms = sorted(a.elapsed_time(b) for a, b in pairs)
+
+    # Warm cache: the same buffer set every step, so the image and its
+    # coefficients stay in the Infinity Cache.
+    warm_ms = None
+    if graphs:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        graphs[0].replay()
+        a.record(stream)
+        for _ in range(K):
+            graphs[0].replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        warm_ms = a.elapsed_time(b) / K
+
     # The same K steps with consecutive steps (independent buffer sets) on two
     # streams, so that one chain's launch gaps overlap the other's kernels.
     concurrent_ms = None
@@ -262,7 +291,7 @@ def run_gpu(args, x_np, scheme):
             (fwd_ms if direction == "forward" else inv_ms).append(e0.elapsed_time(e1) / R)
 
     out = dict(total_ms=total_ms, wall_s=wall, fwd_level_ms=fwd_ms, inv_level_ms=inv_ms,
-               concurrent_ms=concurrent_ms,
+               concurrent_ms=concurrent_ms, step_ms=step_ms, warm_ms=warm_ms,
                fused_levels=list(range(k_tail, L + 1)) if fused else [],
                coef=eager_coef.float().cpu().numpy(), rec=eager_rec.float().cpu().numpy(),
                stored=sets[0][0].float().cpu().numpy(), graph=bool(graphs),
@@ -286,6 +315,38 @@ def load_traffic(kernel_key: str):
     return ent.get("bytes_per_launch")
 
 
+def copy_reference_gbs(reps=10, pairs=2):
+    """Copy bandwidth (read plus write bytes per second) of 1 GiB device
+    buffers, alternating over 4 GiB so that they come from HBM; 1 GiB per
+    copy, so launch gaps do not count. Two copies are timed, the runtime's
+    device-to-device copy and PyTorch's vectorized elementwise kernel (y = x * 1),
+    and the faster one is returned with its name: the practical ceiling the
+    level kernels are compared with."""
+    import torch
+    n = 256 << 20
+    bufs = [(torch.ones(n, device="cuda"), torch.empty(n, device="cuda")) for _ in range(pairs)]
+    ways = {"runtime device copy": lambda a, b: b.copy_(a),
+            "elementwise kernel": lambda a, b: torch.mul(a, 1.0, out=b)}
+    stream = torch.cuda.current_stream()
+    best = (0.0, "")
+    for name, fn in ways.items():
+        for a, b in bufs:
+            fn(a, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for k in range(reps):
+            a, b = bufs[k % pairs]
+            fn(a, b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gbs = 2 * 4 * n / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+        best = max(best, (gbs, name))
+    del bufs
+    torch.cuda.empty_cache()
+    return best
+
+
 def cpu_baseline(x64, wavelet, levels, seconds):
     import numpy as np
     import oracle
@@ -298,6 +359,15 @@ def cpu_baseline(x64, wavelet, levels, seconds):
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
+            break
+    # the same work on one thread, for at least a third of that time
+    reps1, t1 = 0, time.perf_counter()
+    while True:
+        c1 = oracle.forward(x64, wavelet, levels, nthreads=1)
+        oracle.inverse(c1, wavelet, levels, nthreads=1)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= seconds / 3:
             break
     H, W = x64.shape
     cpu_model = ""
@@ -312,7 +382,9 @@ def cpu_baseline(x64, wavelet, levels, seconds):
                 kind="oracle",
                 sample=(f"{reps} x (forward + inverse) of the same {W}x{H} image, "
                         f"{wavelet}, {levels} levels, FP64, OpenMP over rows/columns, "
-                        f"{el:.1f} s; host CPU: {cpu_model}")), coef
+                        f"{el:.1f} s; host CPU: {cpu_model}"),
+                single_thread=dict(value=W * H * reps1 / el1 / 1e9, unit="Gpixel/s", cores=1,
+                                   reps=reps1, seconds=round(el1, 2))), coef
 
 
 def run_batch_workload(args):
@@ -528,6 +600,7 @@ def main():
             r = run_gpu(args, x, sch)
             ablation[sch] = r
 
+    copy_gbs, copy_kind = copy_reference_gbs()
     es = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     lb = level_bytes(W, H, L, es)
     K = args.steps
@@ -552,7 +625,9 @@ def main():
                     traffic=None if all_fused else load_traffic(kernel_key),
                     kernel=(f"{dom} fused levels 1-{L}" if all_fused else f"{dom} level 1")
                     + f" ({args.scheme})",
-                    bytes_per_launch=dom_bytes, avg_launch_ms=round(dom_ms, 5))
+                    bytes_per_launch=dom_bytes, avg_launch_ms=round(dom_ms, 5),
+                    copy_gbs=round(copy_gbs, 1), copy_kind=f"{copy_kind}, 1 GiB",
+                    frac_of_copy=round(achieved / copy_gbs, 4))
 
     def rounded(v):
         return [None if t is None else round(t, 5) for t in v]
@@ -582,6 +657,17 @@ def main():
             note="the same steps, consecutive ones (independent images) on two streams")),
         graph_replay_matches_eager=main_run["replay_matches_eager"],
     )
+    sm = main_run["step_ms"]
+    if sm:
+        def pct(q):
+            return round(sm[min(len(sm) - 1, int(q * len(sm)))], 5)
+        result["step_ms"] = dict(median=pct(0.5), p10=pct(0.1), p90=pct(0.9), samples=len(sm),
+                                 note="single steps, each between its own events")
+    if main_run["warm_ms"]:
+        result["warm_cache"] = dict(
+            value=round(W * H / (main_run["warm_ms"] * 1e-3) / 1e9, 3),
+            ms_per_step=round(main_run["warm_ms"], 5),
+            note="one buffer set replayed: the image and coefficients stay in the Infinity Cache")
     if sep_run is not None:
         s_ms = sep_run["total_ms"] / K
         s1 = max(sep_run["fwd_level_ms"][0], sep_run["inv_level_ms"][0])

@@ -142,8 +142,8 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d,
 
 /* Inverse L-level 2-D DWT: coef (Mallat layout, read only) -> dst.
  * Arguments as for dwt2_forward; tiles[j] and level_events[2j], [2j+1]
- * belong to level j+1 (processed last to first). When dst holds at least
- * 32 MiB, the finest level writes it with non-temporal stores (the values
+ * belong to level j+1 (processed last to first). When dst holds 32 MiB to
+ * 256 MiB, the finest level writes it with non-temporal stores (the values
  * are the same; the lines are not kept in the GPU caches). */
 int dwt2_inverse(const void *coef, const dwt2_desc *coef_d,
                  void *dst, const dwt2_desc *dst_d,

@@ -1,9 +1,9 @@
 """Non-temporal output of the multi-level inverse: when the reconstructed image
-holds at least 32 MiB, the finest level of dwt2_inverse writes it with
+holds 32 MiB to 256 MiB, the finest level of dwt2_inverse writes it with
 non-temporal stores. The values must be bit-identical to the one-level entry
 point, which always writes through the caches, for every storage type and
-scheme, on images just above, at and just below the size limit, with pitched
-and unpitched outputs."""
+scheme, on images at, just inside and just outside both size limits, with
+pitched and unpitched outputs."""
 import pytest
 
 import synthetic
@@ -15,12 +15,14 @@ import paper_1705_08266_amd as dwt  # noqa: E402
 
 TDT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 ES = {"f32": 4, "f16": 2, "bf16": 2}
-LIMIT = 32 << 20
+LIMITS = (32 << 20, 256 << 20)
 
 # (height, width, storage): FP32 4096^2 and FP16 8192x4096 are 64 MiB, FP16
-# 4096^2 exactly 32 MiB, FP32 4096x2040 just below it
+# 4096^2 exactly 32 MiB, FP32 4096x2040 just below it; FP32 8192^2 exactly
+# 256 MiB, FP32 8192x8200 just above it
 CASES = [((4096, 4096), "f32"), ((4096, 8192), "f16"), ((4096, 4096), "bf16"),
-         ((4096, 4096), "f16"), ((2040, 4096), "f32"), ((4094, 4100), "f32")]
+         ((4096, 4096), "f16"), ((2040, 4096), "f32"), ((4094, 4100), "f32"),
+         ((8192, 8192), "f32"), ((8192, 8200), "f32")]
 
 
 def _inverse_one_level_reference(c, wavelet, scheme, out):
@@ -34,7 +36,8 @@ def _inverse_one_level_reference(c, wavelet, scheme, out):
 @pytest.mark.parametrize("shape,dtype", CASES)
 def test_streamed_output_equals_cached(shape, dtype, scheme):
     h, w = shape
-    print(f"stream {dtype} {shape} {scheme} streamed={h * w * ES[dtype] >= LIMIT}", flush=True)
+    streamed = LIMITS[0] <= h * w * ES[dtype] <= LIMITS[1]
+    print(f"stream {dtype} {shape} {scheme} streamed={streamed}", flush=True)
     x = torch.from_numpy(synthetic.uniform_image(h, w, seed=h + w)).to("cuda").to(TDT[dtype])
     c = dwt.forward(x, "cdf97", 1, scheme)
     got = dwt.inverse(c, "cdf97", 1, scheme)
