@@ -210,6 +210,8 @@ TailPlan plan_fwd_tail(int F, int wavelet) {
     return t;
 }
 
+constexpr int kInvTail3Block = 7;   // largest block of a three-level inverse tail, quads
+
 TailPlan plan_inv_tail(int F, int wavelet) {
     const int R = wavelet == DWT2_CDF97 ? 2 : 1;
     TailPlan t;
@@ -224,6 +226,12 @@ TailPlan plan_inv_tail(int F, int wavelet) {
         }
         if (b < B) B = b;
     }
+    // With three fused levels the largest block leaves most of the GPU idle
+    // (100 workgroups at 4096^2, 25 at 2048^2); blocks of at most 7 quads
+    // spread the work over more workgroups with fewer active wavefronts each,
+    // which measured faster there. With two fused levels the largest block
+    // measured faster.
+    if (F == 3 && B > kInvTail3Block) B = kInvTail3Block;
     t.B = B;
     return t;
 }
