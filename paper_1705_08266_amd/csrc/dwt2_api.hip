@@ -210,7 +210,8 @@ TailPlan plan_fwd_tail(int F, int wavelet) {
     return t;
 }
 
-constexpr int kInvTail3Block = 7;   // largest block of a three-level inverse tail, quads
+// Largest extent, in quads, of an inverse tail block at its finest level.
+constexpr int kInvTailFinestBlock = 28;
 
 TailPlan plan_inv_tail(int F, int wavelet) {
     const int R = wavelet == DWT2_CDF97 ? 2 : 1;
@@ -226,12 +227,13 @@ TailPlan plan_inv_tail(int F, int wavelet) {
         }
         if (b < B) B = b;
     }
-    // With three fused levels the largest block leaves most of the GPU idle
-    // (100 workgroups at 4096^2, 25 at 2048^2); blocks of at most 7 quads
-    // spread the work over more workgroups with fewer active wavefronts each,
-    // which measured faster there. With two fused levels the largest block
-    // measured faster.
-    if (F == 3 && B > kInvTail3Block) B = kInvTail3Block;
+    // The largest block leaves most of the GPU idle (100 workgroups for the
+    // three-level tail at 4096^2, 15 for the two-level tail at 7680x4320).
+    // Blocks whose finest level spans at most 28 quads, about half the 64-lane
+    // window, spread the work over more workgroups with fewer active
+    // wavefronts each, which measured faster. Smaller blocks measured slower:
+    // every workgroup still loads and lifts its whole window.
+    if (B > (kInvTailFinestBlock >> (F - 1))) B = kInvTailFinestBlock >> (F - 1);
     t.B = B;
     return t;
 }
