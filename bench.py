@@ -617,7 +617,7 @@ def main():
     dom_bytes = sum(lb) if all_fused else lb[0]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     import paper_1705_08266_amd as dwt
-    _, _, qpl, rows, waves, _, _ = dwt.tile_configs(args.wavelet)[dwt.default_tile(W, H)]
+    _, qpl, rows, waves, _, _ = dwt.tile_configs(args.wavelet)[dwt.default_tile(W, H)]
     kernel_key = (f"{dom}_level1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
                   f"_q{qpl}r{rows}w{waves}")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",

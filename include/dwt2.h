@@ -51,6 +51,11 @@
 extern "C" {
 #endif
 
+/* HIP's stream and event handles (the same declarations as the HIP runtime's
+ * own headers, so this header needs no HIP include; C11 or C++). */
+typedef struct ihipStream_t *hipStream_t;
+typedef struct ihipEvent_t *hipEvent_t;
+
 /* Status codes returned by every entry point that can fail. */
 typedef enum {
     DWT2_OK = 0,
@@ -60,6 +65,8 @@ typedef enum {
     DWT2_ERR_HIP = -4           /* a HIP launch failed; see dwt2_last_hip_error */
 } dwt2_status;
 
+/* The two wavelets the paper evaluates (Sec. 4): CDF 9/7 (two lifting pairs)
+ * and CDF 5/3 (one pair). */
 typedef enum { DWT2_CDF97 = 0, DWT2_CDF53 = 1 } dwt2_wavelet;
 
 /* Only whole-sample symmetric extension is defined. */
@@ -68,16 +75,17 @@ typedef enum { DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC = 0 } dwt2_boundary;
 /* Storage type of a buffer; arithmetic is always FP32. */
 typedef enum { DWT2_F32 = 0, DWT2_F16 = 1, DWT2_BF16 = 2 } dwt2_dtype;
 
-/* NONSEPARABLE: merged spatial steps S_U | T_P per lifting pair (Sec. 3).
- * SEPARABLE: S_U^V | S_U^H | T_P^V | T_P^H per lifting pair (Sec. 2). */
-/* Lifting scheme. NONSEPARABLE: the spatial steps T_P and S_U of Sec. 3 (two
- * steps per lifting pair). SEPARABLE: the horizontal and vertical steps of
- * Sec. 2 (four per pair). Both move horizontal neighbours between lanes of a
- * wavefront (no barrier) and vertical ones through LDS with one barrier per
- * step. The _LDS variants move every neighbour through LDS with a barrier,
- * as a design whose every step synchronises (Sec. 3's setting); they exist to
- * measure the barrier count and support FP32 single-image calls with 2-D
- * tile configurations only (no fused levels, no batches). */
+/* Lifting scheme.
+ *   NONSEPARABLE: the spatial steps T_P and S_U of Sec. 3, two per lifting
+ *     pair, with the constant parts P0 and U0 applied without a barrier.
+ *   SEPARABLE: the horizontal and vertical steps T_P^H, T_P^V, S_U^H, S_U^V
+ *     of Sec. 2, four per lifting pair.
+ * Both move horizontal neighbours between lanes of a wavefront (no barrier)
+ * and vertical ones through LDS with one workgroup barrier per step.
+ *   NONSEPARABLE_LDS, SEPARABLE_LDS: the same steps with every neighbour
+ *     exchange through LDS and a barrier, the setting of Sec. 3 in which
+ *     every step synchronises. They measure the barrier count and support
+ *     FP32 single-image calls only (no fused levels, no batches). */
 typedef enum {
     DWT2_NONSEPARABLE = 0,
     DWT2_SEPARABLE = 1,
@@ -91,13 +99,49 @@ typedef struct {
     int32_t width;
     int32_t height;
     int64_t pitch;
-    int32_t dtype;
+    dwt2_dtype dtype;
 } dwt2_desc;
 
-/* Bytes of FP32 workspace that an L-level transform of a width x height
- * image needs: (W/2)(H/2) floats for L >= 2, plus (W/4)(H/4) for L >= 3.
- * Returns 0 for L = 1 and for invalid sizes. */
-size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels);
+/* Bytes of workspace that an L-level transform of a width x height image of
+ * storage type `dtype` needs. The low-low band between two levels is kept in
+ * FP32 whatever the storage type (intermediate rounding to 16 bits would
+ * double the error of the deep levels), in two ping-pong buffers:
+ * (W/2)(H/2) floats for L >= 2, plus (W/4)(H/4) for L >= 3. Returns 0 for
+ * L = 1 and for invalid sizes or dtypes. */
+size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels, dwt2_dtype dtype);
+
+/* Forward L-level 2-D DWT (Sec. 2, problem statement: each level splits its
+ * input into the LL, HL, LH and HH bands; the lifting steps are those of
+ * Sec. 3 for NONSEPARABLE and Sec. 2 for SEPARABLE).
+ *   src    : the image, described by *src_d (read only, device memory).
+ *   coef   : the Mallat-layout coefficients, described by *coef_d; same
+ *            width, height and dtype as the image. Must not overlap src.
+ *   wavelet, boundary, scheme : enum values above.
+ *   levels : 1..16; width and height must be divisible by 2^levels.
+ *   workspace, workspace_bytes : device scratch of at least
+ *            dwt2_workspace_bytes(width, height, levels, dtype) bytes; may be
+ *            NULL when that is 0. Must not overlap src or coef.
+ *   stream : the HIP stream to enqueue on (NULL: the default stream).
+ * The library picks each level's tile configuration and fuses the trailing
+ * levels whose input has at most DWT2_TAIL_AUTO_PIXELS pixels into one
+ * launch (dwt2_fused_levels). Returns a dwt2_status; on an error nothing is
+ * enqueued. */
+int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
+                 dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                 dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+
+/* Inverse L-level 2-D DWT: coef (Mallat layout, read only) -> dst. The exact
+ * reverse of dwt2_forward: per level, the lifting steps undone in reverse
+ * order with negated coefficients (Sec. 2 and 3 define the forward steps; the
+ * paper does not spell out the inverse). Arguments as for dwt2_forward. When
+ * dst holds 32 MiB to 256 MiB, the finest level writes it with non-temporal
+ * stores (the values are the same; the lines are not kept in the GPU
+ * caches). */
+int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt2_desc *dst_d,
+                 dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                 dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream);
 
 /* Tile id that marks a level as part of the fused tail launch. */
 #define DWT2_TILE_TAIL (-2)
@@ -105,111 +149,88 @@ size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels);
 #define DWT2_TAIL_AUTO_PIXELS (1 << 20)
 
 /* Number of trailing levels that dwt2_forward and dwt2_inverse fuse into
- * one launch when called without tiles (0 when none; never 1). Returns
- * DWT2_ERR_INVALID_ARG for sizes the transform rejects. */
+ * one launch (0 when none; never 1). Multi-scale fusion is the paper's
+ * outlook (Sec. 5). Returns DWT2_ERR_INVALID_ARG for sizes the transform
+ * rejects. */
 int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels);
 
-/* Forward L-level 2-D DWT.
- *   src   : the image, described by *src_d (read only).
- *   coef  : the Mallat-layout coefficients, described by *coef_d; same width,
- *           height and dtype as the image. Must not overlap src.
- *   wavelet, boundary, scheme : enum values above.
- *   levels: 1..16; width and height must be divisible by 2^levels.
+/* dwt2_forward (dwt2_inverse) with two tuning and timing hooks; results are
+ * identical to the plain calls.
  *   tiles : NULL to let the library choose, else `levels` tile ids
  *           (0 <= id < dwt2_tile_config_count()), one per level, or
  *           DWT2_TILE_TAIL for each of the last 2..DWT2_TAIL_MAX levels:
  *           those run fused in one launch (one workgroup computes every
  *           fused level for its block; intermediate low-low bands stay in
- *           LDS). Results are identical either way. Without `tiles` the
- *           library fuses the trailing levels whose input has at most
- *           DWT2_TAIL_AUTO_PIXELS pixels, when there are two or more.
- *   workspace, workspace_bytes : FP32 scratch of at least
- *           dwt2_workspace_bytes(width, height, levels) bytes; may be NULL
- *           when that is 0. Must not overlap src or coef.
- *   level_events : NULL, or 2*levels hipEvent_t handles; events
- *           [2j] and [2j+1] are recorded on `stream` before and after the
- *           launch of level j+1, for per-kernel timing. For fused levels
- *           the first fused level's pair brackets the fused launch and the
- *           other fused levels' pairs are both recorded after it.
- *   stream: hipStream_t to enqueue on.
- * Returns a dwt2_status. */
-int dwt2_forward(const void *src, const dwt2_desc *src_d,
-                 void *coef, const dwt2_desc *coef_d,
-                 int32_t wavelet, int32_t levels, int32_t boundary,
-                 int32_t scheme, const int32_t *tiles,
-                 void *workspace, size_t workspace_bytes,
-                 void *const *level_events, void *stream);
+ *           LDS). Entry j belongs to level j+1.
+ *   level_events : NULL, or 2*levels events; events [2j] and [2j+1] are
+ *           recorded on `stream` before and after the launch of level j+1.
+ *           For fused levels the first fused level's pair brackets the fused
+ *           launch and the other fused levels' pairs are both recorded after
+ *           it. */
+int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
+                    dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                    dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                    const int32_t *tiles, const hipEvent_t *level_events, hipStream_t stream);
+int dwt2_inverse_ex(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt2_desc *dst_d,
+                    dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                    dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                    const int32_t *tiles, const hipEvent_t *level_events, hipStream_t stream);
 
-/* Inverse L-level 2-D DWT: coef (Mallat layout, read only) -> dst.
- * Arguments as for dwt2_forward; tiles[j] and level_events[2j], [2j+1]
- * belong to level j+1 (processed last to first). When dst holds 32 MiB to
- * 256 MiB, the finest level writes it with non-temporal stores (the values
- * are the same; the lines are not kept in the GPU caches). */
-int dwt2_inverse(const void *coef, const dwt2_desc *coef_d,
-                 void *dst, const dwt2_desc *dst_d,
-                 int32_t wavelet, int32_t levels, int32_t boundary,
-                 int32_t scheme, const int32_t *tiles,
-                 void *workspace, size_t workspace_bytes,
-                 void *const *level_events, void *stream);
-
-/* One forward level, one kernel launch (the building block of dwt2_forward).
+/* One forward level, one kernel launch (the building block of dwt2_forward;
+ * Sec. 2: one level of the 2-D transform).
  *   in    : level input, width x height (both even), pitch in_pitch, in_dtype.
  *   ll    : (width/2) x (height/2) low-low output, pitch ll_pitch, ll_dtype.
  *   hl, lh, hh : the three detail bands, each (width/2) x (height/2), sharing
  *           pitch band_pitch and band_dtype.
- * No output may overlap the input. */
-int dwt2_forward_level(const void *in, int64_t in_pitch, int32_t in_dtype,
+ *   tile  : a tile configuration id, or < 0 to let the library choose.
+ * The input and LL are FP32 or the band type. No two of the five buffers may
+ * overlap. */
+int dwt2_forward_level(const void *in, int64_t in_pitch, dwt2_dtype in_dtype,
                        int32_t width, int32_t height,
-                       void *ll, int64_t ll_pitch, int32_t ll_dtype,
+                       void *ll, int64_t ll_pitch, dwt2_dtype ll_dtype,
                        void *hl, void *lh, void *hh, int64_t band_pitch,
-                       int32_t band_dtype,
-                       int32_t wavelet, int32_t scheme, int32_t tile,
-                       void *stream);
+                       dwt2_dtype band_dtype,
+                       dwt2_wavelet wavelet, dwt2_scheme scheme, int32_t tile,
+                       hipStream_t stream);
 
 /* One inverse level: four bands of (width/2) x (height/2) -> out
- * (width x height). `tile` < 0 lets the library choose. */
-int dwt2_inverse_level(const void *ll, int64_t ll_pitch, int32_t ll_dtype,
+ * (width x height). Arguments as for dwt2_forward_level. */
+int dwt2_inverse_level(const void *ll, int64_t ll_pitch, dwt2_dtype ll_dtype,
                        const void *hl, const void *lh, const void *hh,
-                       int64_t band_pitch, int32_t band_dtype,
-                       void *out, int64_t out_pitch, int32_t out_dtype,
+                       int64_t band_pitch, dwt2_dtype band_dtype,
+                       void *out, int64_t out_pitch, dwt2_dtype out_dtype,
                        int32_t width, int32_t height,
-                       int32_t wavelet, int32_t scheme, int32_t tile,
-                       void *stream);
+                       dwt2_wavelet wavelet, dwt2_scheme scheme, int32_t tile,
+                       hipStream_t stream);
 
-/* Kernel configurations ("tiles") compiled into the library. Two kinds:
- *   kind 0, 2-D tile: a workgroup of `waves` wavefronts stacked vertically;
- *     each lane owns `quads_per_lane` consecutive quads of a row and `rows`
- *     quad rows. Of the (64*quads_per_lane) x (waves*rows) quad window the
- *     centre out_x x out_y quads are written; the rest is the lifting halo.
- *   kind 1, stream: each wavefront walks down a strip out_x quads wide,
- *     carrying every lifting step of the level in a row pipeline; `rows` is
- *     its prefetch depth and `waves` the strips segments per workgroup.
- *     out_y is 0: segment lengths are planned per level from the CU count.
- * Returns DWT2_OK or DWT2_ERR_UNSUPPORTED; null out-pointers are skipped. */
+/* Kernel configurations ("tiles") compiled into the library: a workgroup of
+ * `waves` wavefronts stacked vertically; each lane owns `quads_per_lane`
+ * consecutive quads of a row and `rows` quad rows. Of the
+ * (64*quads_per_lane) x (waves*rows) quad window the centre out_x x out_y
+ * quads are written; the rest is the lifting halo. Returns DWT2_OK or
+ * DWT2_ERR_UNSUPPORTED; null out-pointers are skipped. */
 int dwt2_tile_config_count(void);
-int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind,
-                          int32_t *quads_per_lane, int32_t *rows,
-                          int32_t *waves, int32_t *out_x, int32_t *out_y);
+int dwt2_tile_config_info(int32_t tile, dwt2_wavelet wavelet, int32_t *quads_per_lane,
+                          int32_t *rows, int32_t *waves, int32_t *out_x, int32_t *out_y);
 
 /* The tile id the library picks for one level whose full-resolution side
  * (the forward's input, the inverse's output) is width x height pixels of
  * `dtype` storage. */
-int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet,
-                      int32_t scheme, int32_t dtype);
+int dwt2_default_tile(int32_t width, int32_t height, dwt2_wavelet wavelet,
+                      dwt2_scheme scheme, dwt2_dtype dtype);
 
 /* ---- batches of images ---------------------------------------------------
  * Many images of one storage type, wavelet, scheme and level count in few
  * launches: each level is one launch per size class and chunk of up to 36
- * images; the images' level parameters travel in the kernel arguments, so a
- * captured HIP graph of the calls holds everything it needs. A persistent
- * grid of at most the resident number of workgroups strides over the tiles
- * of all images of the launch. */
+ * images, one workgroup per tile; the images' level parameters travel in the
+ * kernel arguments, so a captured HIP graph of the calls holds everything it
+ * needs. */
 typedef struct {
     const void *src;        /* forward: image; inverse: Mallat coefficients */
     int64_t src_pitch;      /* elements */
     void *dst;              /* forward: Mallat coefficients; inverse: image */
     int64_t dst_pitch;      /* elements */
-    void *workspace;        /* FP32 scratch, dwt2_workspace_bytes(width, height, levels) */
+    void *workspace;        /* scratch of dwt2_workspace_bytes(width, height, levels, dtype) */
     size_t workspace_bytes;
     int32_t width, height;  /* divisible by 2^levels */
 } dwt2_image;
@@ -224,15 +245,15 @@ int dwt2_size_class(int32_t width, int32_t height);
 /* Batched L-level forward (inverse) DWT of images[0..n). Each image is
  * checked as by dwt2_forward (dwt2_inverse); src and dst of one image must
  * not overlap, and no two images may share an output or workspace.
- * class_tiles: NULL for the library's choice, else DWT2_SIZE_CLASSES ids of
- * 2-D tile configurations (kind 0), the one used for levels of each class.
+ * class_tiles: NULL for the library's choice, else DWT2_SIZE_CLASSES tile
+ * configuration ids, the one used for levels of each class.
  * Returns a dwt2_status; nothing is enqueued if any image is invalid. */
-int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype,
-                       int32_t wavelet, int32_t levels, int32_t boundary,
-                       int32_t scheme, const int32_t *class_tiles, void *stream);
-int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype,
-                       int32_t wavelet, int32_t levels, int32_t boundary,
-                       int32_t scheme, const int32_t *class_tiles, void *stream);
+int dwt2_forward_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream);
+int dwt2_inverse_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream);
 
 /* One level of one image, as given to dwt2_forward_level (forward) or
  * dwt2_inverse_level (inverse): `full` is the width x height buffer (the
@@ -240,9 +261,9 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype,
  * (width/2) x (height/2) low band, hl/lh/hh the detail bands sharing
  * band_pitch. */
 typedef struct {
-    void *full;  int64_t full_pitch; int32_t full_dtype;
-    void *ll;    int64_t ll_pitch;   int32_t ll_dtype;
-    void *hl, *lh, *hh; int64_t band_pitch; int32_t band_dtype;
+    void *full;  int64_t full_pitch; dwt2_dtype full_dtype;
+    void *ll;    int64_t ll_pitch;   dwt2_dtype ll_dtype;
+    void *hl, *lh, *hh; int64_t band_pitch; dwt2_dtype band_dtype;
     int32_t width, height;
 } dwt2_level_job;
 
@@ -254,11 +275,11 @@ typedef struct {
  * writes. For continuous batching: each call advances every active request
  * by one level. Returns a dwt2_status; nothing is enqueued on an error. */
 int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n,
-                             int32_t wavelet, int32_t scheme,
-                             const int32_t *class_tiles, void *stream);
+                             dwt2_wavelet wavelet, dwt2_scheme scheme,
+                             const int32_t *class_tiles, hipStream_t stream);
 int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n,
-                             int32_t wavelet, int32_t scheme,
-                             const int32_t *class_tiles, void *stream);
+                             dwt2_wavelet wavelet, dwt2_scheme scheme,
+                             const int32_t *class_tiles, hipStream_t stream);
 
 /* Human-readable text of a status code (static storage). */
 const char *dwt2_status_string(int status);

@@ -80,8 +80,10 @@ def _events_arg(events, levels):
     return (ctypes.c_void_p * (2 * levels))(*[e.cuda_event for e in events])
 
 
-def workspace_bytes(width: int, height: int, levels: int) -> int:
-    return int(load().dwt2_workspace_bytes(width, height, levels))
+def workspace_bytes(width: int, height: int, levels: int, dtype=_lib.F32) -> int:
+    """Workspace bytes of an L-level transform (the same for every storage
+    type: intermediate low-low bands are FP32)."""
+    return int(load().dwt2_workspace_bytes(width, height, levels, int(dtype)))
 
 
 def make_workspace(width: int, height: int, levels: int, device=None):
@@ -105,10 +107,14 @@ def forward(x, wavelet="cdf97", levels: int = 1, scheme="nonseparable", out=None
     ws_ptr = workspace.data_ptr() if workspace is not None else None
     ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
     dx, do = _desc(x), _desc(out)
-    st = load().dwt2_forward(x.data_ptr(), ctypes.byref(dx), out.data_ptr(), ctypes.byref(do),
-                             _wavelet(wavelet), levels, _lib.EXT_WHOLE_SAMPLE_SYMMETRIC,
-                             _scheme(scheme), _tiles_arg(tiles, levels), ws_ptr, ws_n,
-                             _events_arg(events, levels), _stream_ptr(stream))
+    args = (x.data_ptr(), ctypes.byref(dx), out.data_ptr(), ctypes.byref(do),
+            _wavelet(wavelet), levels, _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _scheme(scheme),
+            ws_ptr, ws_n)
+    if tiles is None and events is None:
+        st = load().dwt2_forward(*args, _stream_ptr(stream))
+    else:
+        st = load().dwt2_forward_ex(*args, _tiles_arg(tiles, levels),
+                                    _events_arg(events, levels), _stream_ptr(stream))
     _lib.check(st, "dwt2_forward")
     return out
 
@@ -127,10 +133,14 @@ def inverse(c, wavelet="cdf97", levels: int = 1, scheme="nonseparable", out=None
     ws_ptr = workspace.data_ptr() if workspace is not None else None
     ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
     dc, do = _desc(c), _desc(out)
-    st = load().dwt2_inverse(c.data_ptr(), ctypes.byref(dc), out.data_ptr(), ctypes.byref(do),
-                             _wavelet(wavelet), levels, _lib.EXT_WHOLE_SAMPLE_SYMMETRIC,
-                             _scheme(scheme), _tiles_arg(tiles, levels), ws_ptr, ws_n,
-                             _events_arg(events, levels), _stream_ptr(stream))
+    args = (c.data_ptr(), ctypes.byref(dc), out.data_ptr(), ctypes.byref(do),
+            _wavelet(wavelet), levels, _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _scheme(scheme),
+            ws_ptr, ws_n)
+    if tiles is None and events is None:
+        st = load().dwt2_inverse(*args, _stream_ptr(stream))
+    else:
+        st = load().dwt2_inverse_ex(*args, _tiles_arg(tiles, levels),
+                                    _events_arg(events, levels), _stream_ptr(stream))
     _lib.check(st, "dwt2_inverse")
     return out
 
@@ -168,12 +178,11 @@ def inverse_level(ll, hl, lh, hh, out, wavelet="cdf97", scheme="nonseparable", t
 
 
 def tile_configs(wavelet="cdf97"):
-    """[(id, kind, quads_per_lane, rows, waves, out_x, out_y)] compiled in;
-    kind 0 = 2-D tile, 1 = stream."""
+    """[(id, quads_per_lane, rows, waves, out_x, out_y)] compiled in."""
     lib = load()
     out = []
     for t in range(lib.dwt2_tile_config_count()):
-        v = [ctypes.c_int32() for _ in range(6)]
+        v = [ctypes.c_int32() for _ in range(5)]
         _lib.check(lib.dwt2_tile_config_info(t, _wavelet(wavelet), *[ctypes.byref(a) for a in v]))
         out.append((t, *[a.value for a in v]))
     return out

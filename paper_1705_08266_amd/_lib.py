@@ -60,17 +60,23 @@ _LevelJobP = ctypes.POINTER(LevelJob)
 SIZE_CLASSES = 4
 
 SIGNATURES = {
-    "dwt2_workspace_bytes": (_sz, [_i32, _i32, _i32]),
+    "dwt2_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32]),
+    # src, src_d, coef, coef_d, wavelet, levels, boundary, scheme, workspace, bytes, stream
     "dwt2_forward": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
-                                    _ip32, _vp, _sz, _vp, _vp]),
+                                    _vp, _sz, _vp]),
     "dwt2_inverse": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
-                                    _ip32, _vp, _sz, _vp, _vp]),
+                                    _vp, _sz, _vp]),
+    # ... plus tiles and level events before the stream
+    "dwt2_forward_ex": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
+                                       _vp, _sz, _ip32, _vp, _vp]),
+    "dwt2_inverse_ex": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
+                                       _vp, _sz, _ip32, _vp, _vp]),
     "dwt2_forward_level": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _i64, _i32,
                                           _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp]),
     "dwt2_inverse_level": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _i32,
                                           _vp, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _vp]),
     "dwt2_tile_config_count": (ctypes.c_int, []),
-    "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32, _ip32]),
+    "dwt2_tile_config_info": (ctypes.c_int, [_i32, _i32, _ip32, _ip32, _ip32, _ip32, _ip32]),
     "dwt2_default_tile": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
     "dwt2_size_class": (ctypes.c_int, [_i32, _i32]),
     "dwt2_forward_batch": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32, _ip32, _vp]),

@@ -49,7 +49,7 @@ def tune(wavelet="cdf97", scheme="nonseparable", dtype="f32", levels=1, images_p
     if not force and key in cache:
         return list(cache[key]["class_tiles"])
     tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
-    cands = [c[0] for c in tile_configs(wavelet) if c[1] == 0]
+    cands = [c[0] for c in tile_configs(wavelet)]
     best, timings = [], {}
     gen = torch.Generator(device="cuda").manual_seed(12345)
     for c, side in enumerate(CLASS_SIDES):

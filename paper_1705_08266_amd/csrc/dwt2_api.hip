@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -43,21 +44,80 @@ bool valid_wavelet(int w) { return w == DWT2_CDF97 || w == DWT2_CDF53; }
 bool valid_scheme(int s) { return s >= DWT2_NONSEPARABLE && s <= DWT2_SEPARABLE_LDS; }
 // The exchange ablation schemes: FP32 level kernels of 2-D tile configurations.
 bool lds_scheme(int s) { return s == DWT2_NONSEPARABLE_LDS || s == DWT2_SEPARABLE_LDS; }
-bool lds_scheme_ok(int tile, int dt0, int dt1, int dt2) {
-    return dt0 == DWT2_F32 && dt1 == DWT2_F32 && dt2 == DWT2_F32 &&
-           (tile < 0 || kTiles[tile].kind == CFG_TILE);
+bool lds_scheme_ok(int dt0, int dt1, int dt2) {
+    return dt0 == DWT2_F32 && dt1 == DWT2_F32 && dt2 == DWT2_F32;
 }
 
-// Byte span [lo, hi) touched by a rows x cols buffer.
-struct Span {
-    uintptr_t lo, hi;
+// The bytes of a rows x cols buffer with row starts `pitch` bytes apart:
+// {base + r * pitch + c : 0 <= r < rows, 0 <= c < row_bytes}.
+struct Region {
+    uintptr_t base;
+    int64_t rows, row_bytes, pitch;
+    uintptr_t lo() const { return base; }
+    uintptr_t hi() const {   // one past the last byte
+        return rows > 0 ? base + (uintptr_t)((rows - 1) * pitch + row_bytes) : base;
+    }
 };
-Span span_of(const void *p, int64_t rows, int64_t cols, int64_t pitch, int dt) {
-    const uintptr_t lo = (uintptr_t)p;
-    const uint64_t n = rows > 0 ? (uint64_t)((rows - 1) * pitch + cols) : 0;
-    return {lo, lo + n * elem_size(dt)};
+Region region_of(const void *p, int64_t rows, int64_t cols, int64_t pitch, int dt) {
+    const int64_t es = (int64_t)elem_size(dt);
+    return {(uintptr_t)p, rows, cols * es, pitch * es};
 }
-bool overlaps(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+// A contiguous byte range as a one-row region.
+Region bytes_region(const void *p, size_t n) {
+    return {(uintptr_t)p, n > 0 ? 1 : 0, (int64_t)n, (int64_t)n};
+}
+
+// True when two regions share a byte. Regions with the same pitch (the bands
+// of one Mallat array, sub-images of one tensor) are tested exactly: bytes
+// a.base + r1 p + c1 and b.base + r2 p + c2 coincide when, for k = r1 - r2,
+// c1 - c2 = d - k p with d = b.base - a.base; since c1 - c2 lies in
+// (-b.row_bytes, a.row_bytes) and both row lengths are at most p, only the two
+// k next to d / p can qualify; a contiguous range counts as one row of the
+// other region's pitch. Other pairs are tested by their byte spans, which may
+// refuse interleaved buffers of different pitches.
+bool regions_overlap(Region a, Region b) {
+    if (a.rows <= 0 || b.rows <= 0 || a.row_bytes <= 0 || b.row_bytes <= 0) return false;
+    if (!(a.lo() < b.hi() && b.lo() < a.hi())) return false;
+    // a single row (a contiguous range) takes the other region's pitch
+    if (a.rows == 1) a.pitch = b.pitch;
+    if (b.rows == 1) b.pitch = a.pitch;
+    const int64_t p = a.pitch;
+    if (p != b.pitch || a.row_bytes > p || b.row_bytes > p || (a.rows > 1 && p <= 0))
+        return true;   // the byte spans overlap
+    if (a.rows == 1 && b.rows == 1) return true;
+    const int64_t d = (int64_t)(b.base - a.base);   // two's complement difference
+    int64_t k0 = d / p;
+    if (d % p != 0 && d < 0) --k0;                   // floor(d / p)
+    for (int64_t k = k0; k <= k0 + 1; ++k) {
+        if (k < -(b.rows - 1) || k > a.rows - 1) continue;
+        const int64_t c = d - k * p;                 // c1 - c2
+        if (c > -b.row_bytes && c < a.row_bytes) return true;
+    }
+    return false;
+}
+
+// One buffer access of a batched call: which image (or job) makes it, and
+// whether it writes.
+struct Access {
+    Region r;
+    int owner;
+    bool write;
+};
+
+// True when some buffer written for one image (job) shares a byte with any
+// buffer another image (job) reads or writes: such calls would race. Sorted
+// by start address, each access is tested only against the accesses whose
+// byte spans begin inside its own.
+bool cross_conflict(std::vector<Access> &v) {
+    std::sort(v.begin(), v.end(),
+              [](const Access &x, const Access &y) { return x.r.lo() < y.r.lo(); });
+    for (size_t i = 0; i < v.size(); ++i)
+        for (size_t j = i + 1; j < v.size() && v[j].r.lo() < v[i].r.hi(); ++j)
+            if (v[i].owner != v[j].owner && (v[i].write || v[j].write) &&
+                regions_overlap(v[i].r, v[j].r))
+                return true;
+    return false;
+}
 
 bool aligned(const void *p, int64_t pitch, int dt, int vec_elems) {
     size_t bytes = (size_t)vec_elems * elem_size(dt);
@@ -67,61 +127,24 @@ bool aligned(const void *p, int64_t pitch, int dt, int vec_elems) {
 
 int pairs_of(int wavelet) { return wavelet == DWT2_CDF97 ? 2 : 1; }
 
-// Compute units of the current device (queried once per device).
-int device_cus() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-        cached[dev] = cus;
-    }
-    return cached[dev];
-}
-
-// Output quad columns per tile (CFG_TILE) or per strip (CFG_STREAM).
+// Output quads per tile along x and y: the window minus the lifting halo
+// (one lane's quads on each side; one quad row per lifting pair above and
+// below).
 int out_x(int tile, int wavelet) {
-    const TileCfg &c = kTiles[tile];
-    if (c.kind == CFG_TILE) return 64 * c.a - 2 * c.a;
-    const int hxl = (pairs_of(wavelet) + c.a - 1) / c.a;
-    return (64 - 2 * hxl) * c.a;
+    (void)wavelet;
+    return 64 * kTiles[tile].qpl - 2 * kTiles[tile].qpl;
 }
-// Output quad rows per tile (CFG_TILE); 0 for streams (planned per level).
 int out_y(int tile, int wavelet) {
-    const TileCfg &c = kTiles[tile];
-    if (c.kind == CFG_TILE) return c.waves * c.b - 2 * pairs_of(wavelet);
-    return 0;
+    return kTiles[tile].waves * kTiles[tile].rows - 2 * pairs_of(wavelet);
 }
 
-// Work decomposition of one level: tiles (tx x ty) or strips x segments.
+// Tile grid of one level.
 struct Plan {
-    int tiles_x, tiles_y, seg;
+    int tiles_x, tiles_y;
 };
 Plan plan_level(int tile, int wavelet, int nqx, int nqy) {
-    const TileCfg &c = kTiles[tile];
-    Plan p;
-    const int ox = out_x(tile, wavelet);
-    p.tiles_x = (nqx + ox - 1) / ox;
-    if (c.kind == CFG_TILE) {
-        const int oy = out_y(tile, wavelet);
-        p.tiles_y = (nqy + oy - 1) / oy;
-        p.seg = oy;
-    } else {
-        // about per_cu wavefronts per CU; a segment is at least 8 rows so its
-        // lifting halo (two rows per pair) stays a small fraction
-        const int target = device_cus() * c.per_cu;
-        int segs = (target + p.tiles_x - 1) / p.tiles_x;
-        if (segs < 1) segs = 1;
-        int seg = (nqy + segs - 1) / segs;
-        if (seg < 8) seg = 8;
-        if (seg > nqy) seg = nqy;
-        p.seg = seg;
-        p.tiles_y = (nqy + seg - 1) / seg;
-    }
-    return p;
+    const int ox = out_x(tile, wavelet), oy = out_y(tile, wavelet);
+    return {(nqx + ox - 1) / ox, (nqy + oy - 1) / oy};
 }
 
 // Configuration choice for one level: the 128 x 16-quad window held by 8
@@ -133,7 +156,7 @@ Plan plan_level(int tile, int wavelet, int nqx, int nqy) {
 int pick_tile(int width, int height, int wavelet, int storage) {
     (void)wavelet;
     if (storage != DWT2_F32 && (int64_t)width * height > (int64_t)2048 * 2048) return 1;
-    return 10;
+    return 0;
 }
 
 // Sizes of reconstructed image (bytes) that dwt2_inverse writes with
@@ -246,11 +269,10 @@ int size_class(int width, int height) {
     if (px <= 2048 * 2048) return 2;
     return 3;
 }
-// Default 2-D tile per size class.
-// Default 2-D tile per size class and storage type (the same choice as
+// Default tile per size class and storage type (the same choice as
 // pick_tile for a level of that class).
 int class_tile(int cls, int storage) {
-    return (cls == DWT2_SIZE_CLASSES - 1 && storage != DWT2_F32) ? 1 : 10;
+    return (cls == DWT2_SIZE_CLASSES - 1 && storage != DWT2_F32) ? 1 : 0;
 }
 
 int check_level_dims(int32_t width, int32_t height) {
@@ -268,8 +290,8 @@ FwdParams fwd_params(const void *in, int64_t in_pitch, int in_dt, int width, int
     p.hl = hl; p.lh = lh; p.hh = hh; p.band_pitch = band_pitch;
     p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
     const Plan pl = plan_level(tile, wavelet, nqx, nqy);
-    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y; p.seg = pl.seg;
-    const int q = kTiles[tile].a;
+    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y;
+    const int q = kTiles[tile].qpl;
     p.vec_in = aligned(in, in_pitch, in_dt, 2 * q);
     p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
@@ -288,8 +310,8 @@ InvParams inv_params(const void *ll, int64_t ll_pitch, int ll_dt, const void *hl
     p.out = out; p.out_pitch = out_pitch;
     p.w = width; p.h = height; p.nqx = nqx; p.nqy = nqy;
     const Plan pl = plan_level(tile, wavelet, nqx, nqy);
-    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y; p.seg = pl.seg;
-    const int q = kTiles[tile].a;
+    p.tiles_x = pl.tiles_x; p.tiles_y = pl.tiles_y;
+    const int q = kTiles[tile].qpl;
     p.vec_ll = aligned(ll, ll_pitch, ll_dt, q);
     p.vec_band = aligned(hl, band_pitch, band_dt, q) && aligned(lh, band_pitch, band_dt, q) &&
                  aligned(hh, band_pitch, band_dt, q);
@@ -341,19 +363,21 @@ int check_level_args(const void *a, int64_t a_pitch, int a_dt, int32_t width, in
         !valid_wavelet(wavelet) || !valid_scheme(scheme))
         return DWT2_ERR_UNSUPPORTED;
     if (tile >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
-    if (lds_scheme(scheme) && !lds_scheme_ok(tile, a_dt, ll_dt, band_dt)) return DWT2_ERR_UNSUPPORTED;
+    if (lds_scheme(scheme) && !lds_scheme_ok(a_dt, ll_dt, band_dt)) return DWT2_ERR_UNSUPPORTED;
     // The full-resolution and LL buffers are either FP32 or the band type.
     if ((a_dt != band_dt && a_dt != DWT2_F32) || (ll_dt != band_dt && ll_dt != DWT2_F32))
         return DWT2_ERR_INVALID_ARG;
     const int nqx = width / 2, nqy = height / 2;
     if (a_pitch < width || ll_pitch < nqx || band_pitch < nqx) return DWT2_ERR_INVALID_ARG;
-    const Span sa = span_of(a, height, width, a_pitch, a_dt);
-    const Span sl = span_of(ll, nqy, nqx, ll_pitch, ll_dt);
-    const Span s1 = span_of(hl, nqy, nqx, band_pitch, band_dt);
-    const Span s2 = span_of(lh, nqy, nqx, band_pitch, band_dt);
-    const Span s3 = span_of(hh, nqy, nqx, band_pitch, band_dt);
-    if (overlaps(sa, sl) || overlaps(sa, s1) || overlaps(sa, s2) || overlaps(sa, s3))
-        return DWT2_ERR_INVALID_ARG;
+    // no two of the five buffers may share a byte
+    const Region r[5] = {region_of(a, height, width, a_pitch, a_dt),
+                         region_of(ll, nqy, nqx, ll_pitch, ll_dt),
+                         region_of(hl, nqy, nqx, band_pitch, band_dt),
+                         region_of(lh, nqy, nqx, band_pitch, band_dt),
+                         region_of(hh, nqy, nqx, band_pitch, band_dt)};
+    for (int i = 0; i < 5; ++i)
+        for (int j = i + 1; j < 5; ++j)
+            if (regions_overlap(r[i], r[j])) return DWT2_ERR_INVALID_ARG;
     return DWT2_OK;
 }
 
@@ -380,27 +404,41 @@ int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_de
     if (lds_scheme(scheme)) {   // no fused tail; FP32 2-D tiles only
         if (xd->dtype != DWT2_F32) return DWT2_ERR_UNSUPPORTED;
         for (int j = 0; tiles && j < levels; ++j)
-            if (tiles[j] == DWT2_TILE_TAIL || !lds_scheme_ok(tiles[j], DWT2_F32, DWT2_F32, DWT2_F32))
-                return DWT2_ERR_UNSUPPORTED;
+            if (tiles[j] == DWT2_TILE_TAIL) return DWT2_ERR_UNSUPPORTED;
     }
-    const Span sx = span_of(x, H, W, xd->pitch, xd->dtype);
-    const Span sy = span_of(y, H, W, yd->pitch, yd->dtype);
-    if (overlaps(sx, sy)) return DWT2_ERR_INVALID_ARG;
-    const size_t need = dwt2_workspace_bytes(W, H, levels);
+    const Region sx = region_of(x, H, W, xd->pitch, xd->dtype);
+    const Region sy = region_of(y, H, W, yd->pitch, yd->dtype);
+    if (regions_overlap(sx, sy)) return DWT2_ERR_INVALID_ARG;
+    const size_t need = dwt2_workspace_bytes(W, H, levels, DWT2_F32);
     if (need > 0) {
         if (!ws || ws_bytes < need) return DWT2_ERR_WORKSPACE;
-        const Span sw{(uintptr_t)ws, (uintptr_t)ws + need};
-        if (overlaps(sw, sx) || overlaps(sw, sy)) return DWT2_ERR_INVALID_ARG;
+        const Region sw = bytes_region(ws, need);
+        if (regions_overlap(sw, sx) || regions_overlap(sw, sy)) return DWT2_ERR_INVALID_ARG;
     }
     return DWT2_OK;
 }
 
 // Checks one batch image (same rules as the multi-level entry points).
 int check_batch_image(const dwt2_image &im, int32_t dtype, int32_t levels) {
-    const dwt2_desc a{im.width, im.height, im.src_pitch, dtype};
-    const dwt2_desc b{im.width, im.height, im.dst_pitch, dtype};
+    const dwt2_desc a{im.width, im.height, im.src_pitch, (dwt2_dtype)dtype};
+    const dwt2_desc b{im.width, im.height, im.dst_pitch, (dwt2_dtype)dtype};
     return check_multi(im.src, &a, im.dst, &b, DWT2_CDF97, levels, DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC,
                        DWT2_NONSEPARABLE, nullptr, im.workspace, im.workspace_bytes);
+}
+
+// Images of one batch that write a buffer another image reads or writes.
+bool batch_images_conflict(const dwt2_image *images, int n, int dtype, int levels) {
+    std::vector<Access> v;
+    v.reserve(3 * (size_t)(n > 0 ? n : 0));
+    for (int i = 0; i < n; ++i) {
+        const dwt2_image &im = images[i];
+        v.push_back({region_of(im.src, im.height, im.width, im.src_pitch, dtype), i, false});
+        v.push_back({region_of(im.dst, im.height, im.width, im.dst_pitch, dtype), i, true});
+        v.push_back({bytes_region(im.workspace,
+                                  dwt2_workspace_bytes(im.width, im.height, levels, DWT2_F32)),
+                     i, true});
+    }
+    return cross_conflict(v);
 }
 
 // Launch one level of many images: group by size class, then launch the
@@ -431,9 +469,9 @@ int launch_batch_level(const Params *params, const int *tiles_of, const int *cls
     return DWT2_OK;
 }
 
-int record(void *const *events, int idx, hipStream_t s) {
+int record(const hipEvent_t *events, int idx, hipStream_t s) {
     if (!events) return DWT2_OK;
-    const hipError_t e = hipEventRecord((hipEvent_t)events[idx], s);
+    const hipError_t e = hipEventRecord(events[idx], s);
     return e == hipSuccess ? DWT2_OK : hip_fail(e);
 }
 
@@ -456,7 +494,8 @@ const char *dwt2_status_string(int status) {
 
 int dwt2_last_hip_error(void) { return g_last_hip_error; }
 
-size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels) {
+size_t dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels, dwt2_dtype dtype) {
+    if (!valid_dtype(dtype)) return 0;
     if (width < 2 || height < 2 || levels < 1 || levels > 16) return 0;
     if ((width % (1 << levels)) != 0 || (height % (1 << levels)) != 0) return 0;
     if (levels == 1) return 0;
@@ -474,58 +513,65 @@ int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels) {
 
 int dwt2_tile_config_count(void) { return kNumTiles; }
 
-int dwt2_tile_config_info(int32_t tile, int32_t wavelet, int32_t *kind, int32_t *quads_per_lane,
-                          int32_t *rows, int32_t *waves, int32_t *ox, int32_t *oy) {
+int dwt2_tile_config_info(int32_t tile, dwt2_wavelet wavelet, int32_t *quads_per_lane, int32_t *rows,
+                          int32_t *waves, int32_t *ox, int32_t *oy) {
     if (tile < 0 || tile >= kNumTiles || !valid_wavelet(wavelet)) return DWT2_ERR_UNSUPPORTED;
-    if (kind) *kind = kTiles[tile].kind;
-    if (quads_per_lane) *quads_per_lane = kTiles[tile].a;
-    if (rows) *rows = kTiles[tile].b;
+    if (quads_per_lane) *quads_per_lane = kTiles[tile].qpl;
+    if (rows) *rows = kTiles[tile].rows;
     if (waves) *waves = kTiles[tile].waves;
     if (ox) *ox = out_x(tile, wavelet);
     if (oy) *oy = out_y(tile, wavelet);
     return DWT2_OK;
 }
 
-int dwt2_default_tile(int32_t width, int32_t height, int32_t wavelet, int32_t scheme,
-                      int32_t dtype) {
+int dwt2_default_tile(int32_t width, int32_t height, dwt2_wavelet wavelet, dwt2_scheme scheme,
+                      dwt2_dtype dtype) {
     (void)scheme;
     if (check_level_dims(width, height) || !valid_wavelet(wavelet)) return DWT2_ERR_INVALID_ARG;
     return pick_tile(width, height, wavelet, valid_dtype(dtype) ? dtype : DWT2_F32);
 }
 
-int dwt2_forward_level(const void *in, int64_t in_pitch, int32_t in_dtype, int32_t width,
-                       int32_t height, void *ll, int64_t ll_pitch, int32_t ll_dtype, void *hl,
-                       void *lh, void *hh, int64_t band_pitch, int32_t band_dtype,
-                       int32_t wavelet, int32_t scheme, int32_t tile, void *stream) {
+int dwt2_forward_level(const void *in, int64_t in_pitch, dwt2_dtype in_dtype, int32_t width,
+                       int32_t height, void *ll, int64_t ll_pitch, dwt2_dtype ll_dtype, void *hl,
+                       void *lh, void *hh, int64_t band_pitch, dwt2_dtype band_dtype,
+                       dwt2_wavelet wavelet, dwt2_scheme scheme, int32_t tile, hipStream_t stream) {
     const int st = check_level_args(in, in_pitch, in_dtype, width, height, ll, ll_pitch,
                                     ll_dtype, hl, lh, hh, band_pitch, band_dtype, wavelet,
                                     scheme, tile);
     if (st) return st;
     return fwd_level(in, in_pitch, in_dtype, width, height, ll, ll_pitch, ll_dtype, hl, lh, hh,
-                     band_pitch, band_dtype, wavelet, scheme, tile, (hipStream_t)stream);
+                     band_pitch, band_dtype, wavelet, scheme, tile, stream);
 }
 
-int dwt2_inverse_level(const void *ll, int64_t ll_pitch, int32_t ll_dtype, const void *hl,
-                       const void *lh, const void *hh, int64_t band_pitch, int32_t band_dtype,
-                       void *out, int64_t out_pitch, int32_t out_dtype, int32_t width,
-                       int32_t height, int32_t wavelet, int32_t scheme, int32_t tile,
-                       void *stream) {
+int dwt2_inverse_level(const void *ll, int64_t ll_pitch, dwt2_dtype ll_dtype, const void *hl,
+                       const void *lh, const void *hh, int64_t band_pitch, dwt2_dtype band_dtype,
+                       void *out, int64_t out_pitch, dwt2_dtype out_dtype, int32_t width,
+                       int32_t height, dwt2_wavelet wavelet, dwt2_scheme scheme, int32_t tile,
+                       hipStream_t stream) {
     const int st = check_level_args(out, out_pitch, out_dtype, width, height, ll, ll_pitch,
                                     ll_dtype, hl, lh, hh, band_pitch, band_dtype, wavelet,
                                     scheme, tile);
     if (st) return st;
     return inv_level(ll, ll_pitch, ll_dtype, hl, lh, hh, band_pitch, band_dtype, out, out_pitch,
-                     out_dtype, width, height, wavelet, scheme, tile, (hipStream_t)stream);
+                     out_dtype, width, height, wavelet, scheme, tile, stream);
 }
 
 int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
-                 int32_t wavelet, int32_t levels, int32_t boundary, int32_t scheme,
-                 const int32_t *tiles, void *workspace, size_t workspace_bytes,
-                 void *const *level_events, void *stream) {
+                 dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                 dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream) {
+    return dwt2_forward_ex(src, src_d, coef, coef_d, wavelet, levels, boundary, scheme,
+                           workspace, workspace_bytes, nullptr, nullptr, stream);
+}
+
+int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
+                    dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                    dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                    const int32_t *tiles, const hipEvent_t *level_events, hipStream_t stream) {
     int st = check_multi(src, src_d, coef, coef_d, wavelet, levels, boundary, scheme, tiles,
                          workspace, workspace_bytes);
     if (st) return st;
-    const hipStream_t s = (hipStream_t)stream;
+    const hipStream_t s = stream;
     const int32_t W = src_d->width, H = src_d->height, T = src_d->dtype;
     const size_t es = elem_size(T);
     float *ws[2] = {static_cast<float *>(workspace),
@@ -582,13 +628,21 @@ int dwt2_forward(const void *src, const dwt2_desc *src_d, void *coef, const dwt2
 }
 
 int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt2_desc *dst_d,
-                 int32_t wavelet, int32_t levels, int32_t boundary, int32_t scheme,
-                 const int32_t *tiles, void *workspace, size_t workspace_bytes,
-                 void *const *level_events, void *stream) {
+                 dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                 dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream) {
+    return dwt2_inverse_ex(coef, coef_d, dst, dst_d, wavelet, levels, boundary, scheme,
+                           workspace, workspace_bytes, nullptr, nullptr, stream);
+}
+
+int dwt2_inverse_ex(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt2_desc *dst_d,
+                    dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                    dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
+                    const int32_t *tiles, const hipEvent_t *level_events, hipStream_t stream) {
     int st = check_multi(coef, coef_d, dst, dst_d, wavelet, levels, boundary, scheme, tiles,
                          workspace, workspace_bytes);
     if (st) return st;
-    const hipStream_t s = (hipStream_t)stream;
+    const hipStream_t s = stream;
     const int32_t W = coef_d->width, H = coef_d->height, T = coef_d->dtype;
     const size_t es = elem_size(T);
     float *ws[2] = {static_cast<float *>(workspace),
@@ -659,9 +713,9 @@ int dwt2_size_class(int32_t width, int32_t height) {
     return size_class(width, height);
 }
 
-int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
-                       int32_t levels, int32_t boundary, int32_t scheme,
-                       const int32_t *class_tiles, void *stream) {
+int dwt2_forward_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
     if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
     if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
         boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
@@ -669,14 +723,14 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
         ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
-        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
-            return DWT2_ERR_UNSUPPORTED;
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
     }
     for (int i = 0; i < n; ++i) {
         const int st = check_batch_image(images[i], dtype, levels);
         if (st) return st;
     }
-    const hipStream_t s = (hipStream_t)stream;
+    if (batch_images_conflict(images, n, dtype, levels)) return DWT2_ERR_INVALID_ARG;
+    const hipStream_t s = stream;
     const size_t es = elem_size(dtype);
     std::vector<FwdParams> params_v(n > 0 ? n : 1);
     std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
@@ -716,9 +770,9 @@ int dwt2_forward_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
     return st;
 }
 
-int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
-                       int32_t levels, int32_t boundary, int32_t scheme,
-                       const int32_t *class_tiles, void *stream) {
+int dwt2_inverse_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
+                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
     if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
     if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
         boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
@@ -726,14 +780,14 @@ int dwt2_inverse_batch(const dwt2_image *images, int32_t n, int32_t dtype, int32
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
         ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
-        if (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE)
-            return DWT2_ERR_UNSUPPORTED;
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
     }
     for (int i = 0; i < n; ++i) {
         const int st = check_batch_image(images[i], dtype, levels);
         if (st) return st;
     }
-    const hipStream_t s = (hipStream_t)stream;
+    if (batch_images_conflict(images, n, dtype, levels)) return DWT2_ERR_INVALID_ARG;
+    const hipStream_t s = stream;
     const size_t es = elem_size(dtype);
     std::vector<InvParams> params_v(n > 0 ? n : 1);
     std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
@@ -787,16 +841,14 @@ struct JobKey {
 
 template <bool INV>
 int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t scheme,
-                const int32_t *class_tiles, void *stream) {
+                const int32_t *class_tiles, hipStream_t stream) {
     if (n < 0 || (n > 0 && !jobs)) return DWT2_ERR_INVALID_ARG;
     if (!valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme))
         return DWT2_ERR_UNSUPPORTED;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
         ctile[c] = class_tiles ? class_tiles[c] : -1;   // -1: by storage, per group below
-        if (class_tiles &&
-            (ctile[c] < 0 || ctile[c] >= kNumTiles || kTiles[ctile[c]].kind != CFG_TILE))
-            return DWT2_ERR_UNSUPPORTED;
+        if (class_tiles && (ctile[c] < 0 || ctile[c] >= kNumTiles)) return DWT2_ERR_UNSUPPORTED;
     }
     for (int i = 0; i < n; ++i) {
         const dwt2_level_job &j = jobs[i];
@@ -805,7 +857,21 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
                                         j.band_pitch, j.band_dtype, wavelet, scheme, 0);
         if (st) return st;
     }
-    const hipStream_t s = (hipStream_t)stream;
+    {   // the forward writes the bands and reads `full`; the inverse the reverse
+        std::vector<Access> v;
+        v.reserve(5 * (size_t)(n > 0 ? n : 0));
+        for (int i = 0; i < n; ++i) {
+            const dwt2_level_job &j = jobs[i];
+            const int nqx = j.width / 2, nqy = j.height / 2;
+            v.push_back({region_of(j.full, j.height, j.width, j.full_pitch, j.full_dtype), i, INV});
+            v.push_back({region_of(j.ll, nqy, nqx, j.ll_pitch, j.ll_dtype), i, !INV});
+            v.push_back({region_of(j.hl, nqy, nqx, j.band_pitch, j.band_dtype), i, !INV});
+            v.push_back({region_of(j.lh, nqy, nqx, j.band_pitch, j.band_dtype), i, !INV});
+            v.push_back({region_of(j.hh, nqy, nqx, j.band_pitch, j.band_dtype), i, !INV});
+        }
+        if (cross_conflict(v)) return DWT2_ERR_INVALID_ARG;
+    }
+    const hipStream_t s = stream;
     std::vector<JobKey> keys(n > 0 ? n : 1);
     std::vector<char> done(n > 0 ? n : 1);
     for (int i = 0; i < n; ++i) {
@@ -858,13 +924,13 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
 
 extern "C" {
 
-int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet,
-                             int32_t scheme, const int32_t *class_tiles, void *stream) {
+int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                             dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
     return level_batch<false>(jobs, n, wavelet, scheme, class_tiles, stream);
 }
 
-int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet,
-                             int32_t scheme, const int32_t *class_tiles, void *stream) {
+int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                             dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
     return level_batch<true>(jobs, n, wavelet, scheme, class_tiles, stream);
 }
 

@@ -23,7 +23,6 @@ struct FwdParams {
     int64_t band_pitch;
     int32_t w, h, nqx, nqy;
     int32_t tiles_x, tiles_y;
-    int32_t seg;                        // streaming kernels: output rows per segment
     int32_t vec_in, vec_ll, vec_band;   // 1 when vector accesses are aligned
 };
 
@@ -36,7 +35,6 @@ struct InvParams {
     int64_t out_pitch;
     int32_t w, h, nqx, nqy;
     int32_t tiles_x, tiles_y;
-    int32_t seg;                         // streaming kernels: output rows per segment
     uint8_t vec_ll, vec_band, vec_out;   // 1 when vector accesses are aligned
     uint8_t stream_out;                  // 1: vector output stores are non-temporal
 };

@@ -5,40 +5,24 @@
 #include <utility>
 
 #include "dwt2_kernels.hpp"
-#include "dwt2_stream.hpp"
 #include "dwt2_tail.hpp"
 
 namespace dwt2 {
 
-enum : int { CFG_TILE = 0, CFG_STREAM = 1 };
-
-// A compiled kernel configuration.
-//   CFG_TILE:   a = quads per lane, b = quad rows per lane, waves stacked in y;
-//               window (64a) x (waves*b) quads, one tile per workgroup.
-//   CFG_STREAM: a = quads per lane, b = prefetch depth in rows, `waves`
-//               independent strip segments per workgroup; segments are sized
-//               so that about `per_cu` wavefronts per CU cover the level.
+// A compiled 2-D tile configuration: a workgroup of `waves` wavefronts stacked
+// vertically, each lane holding `qpl` consecutive quads of a row and `rows`
+// quad rows; the window is (64 qpl) x (waves rows) quads, one per workgroup.
 struct TileCfg {
-    int kind;
-    int a;
-    int b;
+    int qpl;
+    int rows;
     int waves;
-    int per_cu;
 };
 
 constexpr TileCfg kTiles[] = {
-    {CFG_TILE, 2, 8, 4, 0},      // 0: 128 x 32 window, 256 threads
-    {CFG_TILE, 2, 4, 4, 0},      // 1: 128 x 16
-    {CFG_TILE, 2, 8, 1, 0},      // 2: 128 x 8, one wavefront, no barriers
-    {CFG_TILE, 2, 4, 8, 0},      // 3: 128 x 32, 512 threads
-    {CFG_STREAM, 2, 8, 4, 8},    // 4: strips of 124 quads (9/7)
-    {CFG_STREAM, 2, 6, 4, 8},    // 5
-    {CFG_STREAM, 1, 8, 4, 8},    // 6: strips of 60 quads (9/7)
-    {CFG_STREAM, 2, 8, 4, 4},    // 7
-    {CFG_STREAM, 2, 8, 4, 16},   // 8
-    {CFG_STREAM, 4, 4, 4, 8},    // 9: strips of 248 quads (prefetch 2 rows)
-    {CFG_TILE, 2, 2, 8, 0},      // 10: 128 x 16, 512 threads of 2 rows
-    {CFG_TILE, 2, 3, 8, 0},      // 11: 128 x 24, 512 threads of 3 rows
+    {2, 2, 8},   // 0: 128 x 16 window, 512 threads (FP32 default)
+    {2, 4, 4},   // 1: 128 x 16, 256 threads (16-bit default above 2048^2)
+    {2, 3, 8},   // 2: 128 x 24, 512 threads
+    {2, 8, 1},   // 3: 128 x 8, one wavefront (no workgroup barriers)
 };
 constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
@@ -50,28 +34,16 @@ using InvLauncher = hipError_t (*)(const InvParams &, hipStream_t);
 template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
 hipError_t launch_fwd(const FwdParams &p, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    const int tasks = p.tiles_x * p.tiles_y;
-    if constexpr (c.kind == CFG_TILE) {
-        hipLaunchKernelGGL((fwd_level_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>),
-                           dim3(tasks), dim3(64 * c.waves), 0, s, p);
-    } else {
-        hipLaunchKernelGGL((fwd_stream_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>),
-                           dim3((tasks + c.waves - 1) / c.waves), dim3(64 * c.waves), 0, s, p);
-    }
+    hipLaunchKernelGGL((fwd_level_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>),
+                       dim3(p.tiles_x * p.tiles_y), dim3(64 * c.waves), 0, s, p);
     return hipGetLastError();
 }
 
 template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
 hipError_t launch_inv(const InvParams &p, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    const int tasks = p.tiles_x * p.tiles_y;
-    if constexpr (c.kind == CFG_TILE) {
-        hipLaunchKernelGGL((inv_level_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>),
-                           dim3(tasks), dim3(64 * c.waves), 0, s, p);
-    } else {
-        hipLaunchKernelGGL((inv_stream_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>),
-                           dim3((tasks + c.waves - 1) / c.waves), dim3(64 * c.waves), 0, s, p);
-    }
+    hipLaunchKernelGGL((inv_level_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>),
+                       dim3(p.tiles_x * p.tiles_y), dim3(64 * c.waves), 0, s, p);
     return hipGetLastError();
 }
 
@@ -89,10 +61,8 @@ int resident_blocks(const void *kernel, int block_threads);
 template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
 hipError_t launch_fwd_batch(const FwdBatch &b, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    if constexpr (c.kind != CFG_TILE) {
-        return hipErrorInvalidValue;
-    } else {
-        const auto k = fwd_batch_kernel<WV, SCH, c.a, c.b, c.waves, TIN, TLL, TB>;
+    {
+        const auto k = fwd_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>;
         const int total = b.tile_start[b.n];
         int grid = total;
         if constexpr (kBatchPersistent) {
@@ -108,10 +78,8 @@ hipError_t launch_fwd_batch(const FwdBatch &b, hipStream_t s) {
 template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
 hipError_t launch_inv_batch(const InvBatch &b, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    if constexpr (c.kind != CFG_TILE) {
-        return hipErrorInvalidValue;
-    } else {
-        const auto k = inv_batch_kernel<WV, SCH, c.a, c.b, c.waves, TLL, TB, TOUT>;
+    {
+        const auto k = inv_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>;
         const int total = b.tile_start[b.n];
         int grid = total;
         if constexpr (kBatchPersistent) {
@@ -245,26 +213,17 @@ constexpr InvTailTable make_inv_tail_table() {
              {inv_tail_depths<T, CDF53, NONSEP>(), inv_tail_depths<T, CDF53, SEP>()}}};
 }
 
-// The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels of the 2-D
-// tile configurations only, index [wavelet][scheme - NONSEP_LDS][config].
+// The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels only, index [wavelet][scheme - NONSEP_LDS][config].
 using FwdLdsTable = std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>;
 using InvLdsTable = std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>;
 
 template <int WV, int SCH, int T>
 hipError_t launch_fwd_lds(const FwdParams &p, hipStream_t s) {
-    if constexpr (kTiles[T].kind != CFG_TILE) {
-        return hipErrorInvalidValue;
-    } else {
-        return launch_fwd<WV, SCH, T, float, float, float>(p, s);
-    }
+    return launch_fwd<WV, SCH, T, float, float, float>(p, s);
 }
 template <int WV, int SCH, int T>
 hipError_t launch_inv_lds(const InvParams &p, hipStream_t s) {
-    if constexpr (kTiles[T].kind != CFG_TILE) {
-        return hipErrorInvalidValue;
-    } else {
-        return launch_inv<WV, SCH, T, float, float, float>(p, s);
-    }
+    return launch_inv<WV, SCH, T, float, float, float>(p, s);
 }
 template <int WV, int SCH, int... I>
 constexpr std::array<FwdLauncher, kNumTiles> fwd_lds_tiles(std::integer_sequence<int, I...>) {

@@ -36,30 +36,74 @@ def test_every_declared_symbol_is_exported_and_bound():
         assert n in _lib.SIGNATURES, f"{n} missing from the Python binding"
 
 
+# The boundary's core prototypes, written as the scope table states them
+# (parameter names aside). Compiling them after the header makes the C
+# compiler reject any difference in a parameter or return type.
+SECTION_8B_PROTOTYPES = """
+size_t      dwt2_workspace_bytes(int32_t width, int32_t height, int32_t levels, dwt2_dtype dtype);
+int         dwt2_forward(const void* src, const dwt2_desc* src_d, void* coef, const dwt2_desc* coef_d,
+                         dwt2_wavelet w, int32_t levels, dwt2_boundary b, dwt2_scheme s,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+int         dwt2_inverse(const void* coef, const dwt2_desc* coef_d, void* dst, const dwt2_desc* dst_d,
+                         dwt2_wavelet w, int32_t levels, dwt2_boundary b, dwt2_scheme s,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+const char* dwt2_status_string(int status);
+int         dwt2_last_hip_error(void);
+"""
+
+
+def test_header_matches_the_scope_prototypes(tmp_path):
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "proto.c"
+    src.write_text('#include "dwt2.h"\n' + SECTION_8B_PROTOTYPES)
+    r = subprocess.run([cc, "-std=c11", "-Wall", "-Werror", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    # a wrong prototype is rejected (the check above has teeth)
+    bad = tmp_path / "bad.c"
+    bad.write_text('#include "dwt2.h"\n'
+                   "int dwt2_forward(const void*, const dwt2_desc*, void*, const dwt2_desc*,"
+                   " dwt2_wavelet, int32_t, dwt2_boundary, dwt2_scheme, const int32_t*,"
+                   " void*, size_t, void* const*, hipStream_t);\n")
+    r = subprocess.run([cc, "-std=c11", "-fsyntax-only", "-I", os.path.dirname(HEADER),
+                        str(bad)], capture_output=True, text=True)
+    assert r.returncode != 0
+
+
+def test_core_entry_points_take_the_scope_arguments():
+    """dwt2_forward / dwt2_inverse take exactly the 11 arguments; tuning and
+    timing hooks live in the _ex calls."""
+    assert len(_lib.SIGNATURES["dwt2_forward"][1]) == 11
+    assert len(_lib.SIGNATURES["dwt2_inverse"][1]) == 11
+    assert len(_lib.SIGNATURES["dwt2_forward_ex"][1]) == 13
+    assert len(_lib.SIGNATURES["dwt2_workspace_bytes"][1]) == 4
+
+
 def test_workspace_bytes():
     lib = _lib.load()
-    assert lib.dwt2_workspace_bytes(64, 64, 1) == 0
-    assert lib.dwt2_workspace_bytes(64, 64, 2) == 32 * 32 * 4
-    assert lib.dwt2_workspace_bytes(64, 64, 3) == (32 * 32 + 16 * 16) * 4
-    assert lib.dwt2_workspace_bytes(4096, 4096, 5) == (2048 * 2048 + 1024 * 1024) * 4
-    assert lib.dwt2_workspace_bytes(48, 64, 5) == 0          # 48 not divisible by 32
-    assert lib.dwt2_workspace_bytes(64, 64, 0) == 0
+    for dt in (_lib.F32, _lib.F16, _lib.BF16):     # intermediate LL is FP32 for every dtype
+        assert lib.dwt2_workspace_bytes(64, 64, 1, dt) == 0
+        assert lib.dwt2_workspace_bytes(64, 64, 2, dt) == 32 * 32 * 4
+        assert lib.dwt2_workspace_bytes(64, 64, 3, dt) == (32 * 32 + 16 * 16) * 4
+        assert lib.dwt2_workspace_bytes(4096, 4096, 5, dt) == (2048 * 2048 + 1024 * 1024) * 4
+        assert lib.dwt2_workspace_bytes(48, 64, 5, dt) == 0      # 48 not divisible by 32
+        assert lib.dwt2_workspace_bytes(64, 64, 0, dt) == 0
+    assert lib.dwt2_workspace_bytes(64, 64, 2, 7) == 0          # unknown dtype
 
 
 def test_tile_configs_cover_the_lifting_halo():
     for w, np_ in (("cdf97", 2), ("cdf53", 1)):
         cfgs = dwt.tile_configs(w)
         assert len(cfgs) >= 4
-        kinds = {c[1] for c in cfgs}
-        assert kinds == {0, 1}
-        for (t, kind, qpl, rows, waves, ox, oy) in cfgs:
-            if kind == 0:                            # 2-D tile: one halo lane each side
-                assert qpl >= np_
-                assert ox == 64 * qpl - 2 * qpl
-                assert oy == waves * rows - 2 * np_ > 0
-            else:                                    # stream: ceil(np/qpl) halo lanes
-                hxl = -(-np_ // qpl)
-                assert ox == (64 - 2 * hxl) * qpl and oy == 0
+        for (t, qpl, rows, waves, ox, oy) in cfgs:   # one halo lane each side
+            assert qpl >= np_
+            assert ox == 64 * qpl - 2 * qpl
+            assert oy == waves * rows - 2 * np_ > 0
 
 
 def test_default_tile_is_valid():
@@ -84,8 +128,11 @@ def _fwd(src=FAKE, sd=None, dst=FAKE + (1 << 30), dd=None, wavelet=0, levels=1,
     lib = _lib.load()
     sd = sd or _lib.Desc(64, 64, 64, _lib.F32)
     dd = dd or _lib.Desc(64, 64, 64, _lib.F32)
-    return lib.dwt2_forward(src, ctypes.byref(sd), dst, ctypes.byref(dd), wavelet, levels,
-                            boundary, scheme, tiles, ws, wsb, None, None)
+    if tiles is None:
+        return lib.dwt2_forward(src, ctypes.byref(sd), dst, ctypes.byref(dd), wavelet, levels,
+                                boundary, scheme, ws, wsb, None)
+    return lib.dwt2_forward_ex(src, ctypes.byref(sd), dst, ctypes.byref(dd), wavelet, levels,
+                               boundary, scheme, ws, wsb, tiles, None, None)
 
 
 def test_forward_argument_errors():
@@ -137,8 +184,8 @@ def test_fused_tail_tile_ids():
 
 
 def test_exchange_ablation_scheme_limits():
-    """The LDS-exchange schemes take FP32 and 2-D tile configurations only,
-    and no fused levels or batches."""
+    """The LDS-exchange schemes take FP32 only, and no fused levels or
+    batches."""
     U, W = _lib.ERR_UNSUPPORTED, _lib.ERR_WORKSPACE
     for sch in (_lib.NONSEPARABLE_LDS, _lib.SEPARABLE_LDS):
         assert _fwd(levels=2, scheme=sch) == W                    # accepted up to the workspace
@@ -146,8 +193,6 @@ def test_exchange_ablation_scheme_limits():
                     scheme=sch) == U
         assert _fwd(levels=2, scheme=sch, tiles=(ctypes.c_int32 * 2)(_lib.TILE_TAIL,
                                                                       _lib.TILE_TAIL)) == U
-        stream_cfg = [c[0] for c in __import__("paper_1705_08266_amd").tile_configs() if c[1] == 1][0]
-        assert _fwd(scheme=sch, tiles=(ctypes.c_int32 * 1)(stream_cfg)) == U
         lib = _lib.load()
         assert lib.dwt2_forward_batch(None, 0, _lib.F32, 0, 1, 0, sch, None, None) == U
         assert lib.dwt2_forward_level_batch(None, 0, 0, sch, None, None) == U
@@ -158,9 +203,11 @@ def test_inverse_argument_errors():
     lib = _lib.load()
     d = _lib.Desc(32, 32, 32, _lib.F32)
     assert lib.dwt2_inverse(None, ctypes.byref(d), FAKE, ctypes.byref(d), 0, 1, 0, 0,
-                            None, None, 0, None, None) == _lib.ERR_INVALID_ARG
+                            None, 0, None) == _lib.ERR_INVALID_ARG
     assert lib.dwt2_inverse(FAKE, ctypes.byref(d), FAKE + 8, ctypes.byref(d), 0, 1, 0, 0,
-                            None, None, 0, None, None) == _lib.ERR_INVALID_ARG
+                            None, 0, None) == _lib.ERR_INVALID_ARG
+    assert lib.dwt2_inverse_ex(FAKE, ctypes.byref(d), FAKE + 8, ctypes.byref(d), 0, 1, 0, 0,
+                               None, 0, None, None, None) == _lib.ERR_INVALID_ARG
 
 
 def test_level_argument_errors():
