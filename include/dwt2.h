@@ -143,6 +143,27 @@ int dwt2_inverse(const void *coef, const dwt2_desc *coef_d, void *dst, const dwt
                  dwt2_scheme scheme, void *workspace, size_t workspace_bytes,
                  hipStream_t stream);
 
+/* ---- a forward call that allocates nothing --------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as dwt2_forward, with the workspace taken from a library-owned
+ * array of DWT2_STATIC_WORKSPACE_BYTES bytes in device memory. Each GPU the
+ * library runs on holds its own copy of that array from the library's load
+ * until the process ends. The call allocates and frees nothing (on its first
+ * call on a device it looks up the array's address there).
+ *   Arguments, results and errors as for dwt2_forward, plus
+ *   DWT2_ERR_WORKSPACE when dwt2_workspace_bytes(width, height, levels,
+ *   dtype) exceeds DWT2_STATIC_WORKSPACE_BYTES (e.g. 16384^2 with L >= 2).
+ *   Every call on one GPU shares that GPU's array: calls that may overlap in
+ *   time on one GPU (different streams, or host threads enqueueing
+ *   concurrently) race on it and give wrong results. Each call overwrites
+ *   every byte of the array it reads, so no state carries over between
+ *   calls. */
+#define DWT2_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int dwt2_forward_no_alloc(const void *src, const dwt2_desc *src_d, void *coef,
+                          const dwt2_desc *coef_d, dwt2_wavelet wavelet, int32_t levels,
+                          dwt2_boundary boundary, dwt2_scheme scheme, hipStream_t stream);
+
 /* Tile id that marks a level as part of the fused tail launch. */
 #define DWT2_TILE_TAIL (-2)
 #define DWT2_TAIL_MAX 3

@@ -119,6 +119,23 @@ def forward(x, wavelet="cdf97", levels: int = 1, scheme="nonseparable", out=None
     return out
 
 
+def forward_no_alloc(x, out, wavelet="cdf97", levels: int = 1, scheme="nonseparable",
+                     stream=None):
+    """:func:`forward` into a caller-provided `out`, with the library's own
+    device workspace: the call allocates nothing (for graph capture and
+    allocation-free loops). Calls on one GPU share that workspace and must not
+    overlap in time."""
+    _check_2d(x, "x")
+    _check_2d(out, "out")
+    dx, do = _desc(x), _desc(out)
+    st = load().dwt2_forward_no_alloc(x.data_ptr(), ctypes.byref(dx), out.data_ptr(),
+                                      ctypes.byref(do), _wavelet(wavelet), levels,
+                                      _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _scheme(scheme),
+                                      _stream_ptr(stream))
+    _lib.check(st, "dwt2_forward_no_alloc")
+    return out
+
+
 def inverse(c, wavelet="cdf97", levels: int = 1, scheme="nonseparable", out=None,
             workspace=None, tiles=None, events=None, stream=None):
     """Inverse of :func:`forward`."""

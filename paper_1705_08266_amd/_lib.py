@@ -19,6 +19,7 @@ NONSEPARABLE, SEPARABLE, NONSEPARABLE_LDS, SEPARABLE_LDS = 0, 1, 2, 3
 TILE_TAIL = -2            # tiles[j] of a level that runs in the fused tail launch
 TAIL_MAX = 3
 TAIL_AUTO_PIXELS = 1 << 20
+STATIC_WORKSPACE_BYTES = 64 << 20   # DWT2_STATIC_WORKSPACE_BYTES
 
 # Every function declared in include/dwt2.h: name -> (restype, argtypes)
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -71,6 +72,8 @@ SIGNATURES = {
                                        _vp, _sz, _ip32, _vp, _vp]),
     "dwt2_inverse_ex": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
                                        _vp, _sz, _ip32, _vp, _vp]),
+    "dwt2_forward_no_alloc": (ctypes.c_int, [_vp, _DescP, _vp, _DescP, _i32, _i32, _i32, _i32,
+                                             _vp]),
     "dwt2_forward_level": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _i64, _i32,
                                           _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp]),
     "dwt2_inverse_level": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _i32,

@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -477,7 +478,56 @@ int record(const hipEvent_t *events, int idx, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+// Workspace of dwt2_forward_no_alloc: a device array of the library's own,
+// one copy per GPU (the code object's data), never allocated or freed by a
+// call. Host code uses it only through the address hipGetSymbolAddress
+// returns on each device: the array's name is a host-side stand-in.
+static __device__ __align__(256) unsigned char scratch[DWT2_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, looked up on the first call on
+// that device (with the device current) and kept.
+int scratch_on_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return DWT2_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!p) return hip_fail(hipErrorInvalidSymbol);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DWT2_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int dwt2_forward_no_alloc(const void *src, const dwt2_desc *src_d, void *coef,
+                          const dwt2_desc *coef_d, dwt2_wavelet wavelet, int32_t levels,
+                          dwt2_boundary boundary, dwt2_scheme scheme, hipStream_t stream) {
+    // every argument check that needs no workspace, then the size limit
+    int st = check_multi(src, src_d, coef, coef_d, wavelet, levels, boundary, scheme, nullptr,
+                         nullptr, 0);
+    if (st != DWT2_OK && st != DWT2_ERR_WORKSPACE) return st;
+    if (dwt2_workspace_bytes(src_d->width, src_d->height, levels, src_d->dtype) >
+        DWT2_STATIC_WORKSPACE_BYTES)
+        return DWT2_ERR_WORKSPACE;
+    void *ws = nullptr;
+    if ((st = scratch_on_current_device(&ws))) return st;
+    return dwt2_forward_ex(src, src_d, coef, coef_d, wavelet, levels, boundary, scheme, ws,
+                           DWT2_STATIC_WORKSPACE_BYTES, nullptr, nullptr, stream);
+}
 
 int dwt2_version(void) { return 100; }
 

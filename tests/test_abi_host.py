@@ -232,3 +232,22 @@ def test_binding_refuses_cpu_tensors():
     x = torch.zeros(8, 8)
     with pytest.raises(ValueError):
         dwt.forward(x)
+
+
+def test_no_alloc_checks_before_touching_the_device():
+    """dwt2_forward_no_alloc validates like dwt2_forward, then refuses sizes
+    whose workspace exceeds its static array, all before any HIP call."""
+    lib = _lib.load()
+    big = _lib.Desc(16384, 16384, 16384, _lib.F32)
+    assert lib.dwt2_forward_no_alloc(FAKE, ctypes.byref(big), FAKE + (1 << 32), ctypes.byref(big),
+                                     0, 5, 0, 0, None) == _lib.ERR_WORKSPACE
+    d = _lib.Desc(64, 64, 64, _lib.F32)
+    assert lib.dwt2_forward_no_alloc(None, ctypes.byref(d), FAKE, ctypes.byref(d),
+                                     0, 2, 0, 0, None) == _lib.ERR_INVALID_ARG
+    assert lib.dwt2_forward_no_alloc(FAKE, ctypes.byref(d), FAKE + 8, ctypes.byref(d),
+                                     0, 2, 0, 0, None) == _lib.ERR_INVALID_ARG   # overlap
+    assert lib.dwt2_forward_no_alloc(FAKE, ctypes.byref(d), FAKE + (1 << 20), ctypes.byref(d),
+                                     5, 2, 0, 0, None) == _lib.ERR_UNSUPPORTED
+    assert _lib.STATIC_WORKSPACE_BYTES == 64 << 20
+    header = open(HEADER).read()
+    assert "#define DWT2_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)" in header
