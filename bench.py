@@ -389,7 +389,10 @@ def cpu_baseline(x64, wavelet, levels, seconds):
 
 def run_batch_workload(args):
     """256 uneven images (sides log-uniform in [64, 4096], multiples of 32),
-    3-level forward, one captured graph of batched launches."""
+    3-level forward, planned once: each level is one launch over all images
+    per tile configuration in use, captured in one graph. Times the default
+    tiles with one workgroup per tile and with a persistent grid, then the
+    per-class tuned tiles with the faster grid."""
     import numpy as np
     import torch
     import synthetic
@@ -400,28 +403,48 @@ def run_batch_workload(args):
     tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
     sizes = synthetic.batch_sizes(args.batch, 64, 4096, 32, seed=synthetic.SEED_BASE + 4)
     print(f"[bench] batch of {len(sizes)} images, {sum(w * h for w, h in sizes) / 1e6:.1f} Mpx, "
-          f"L={L}; tuning tiles per size class", file=sys.stderr, flush=True)
-    class_tiles = autotune.tune(args.wavelet, args.scheme, args.dtype, L,
-                                cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"))
+          f"L={L}", file=sys.stderr, flush=True)
     imgs = []
     for i, (w, h) in enumerate(sizes):
         x = synthetic.uniform_image(h, w, seed=synthetic.SEED_BASE + 4 + i)
         imgs.append(torch.from_numpy(x).to("cuda").to(tdt))
-    plan = BatchPlan.forward(imgs, L, args.wavelet, args.scheme, class_tiles)
-    plan.capture()
-    for _ in range(args.warmup):
-        plan.replay()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        plan.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
     es = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     alg = sum(sum(level_bytes(w, h, L, es)) for w, h in sizes)
+
+    def time_plan(plan):
+        plan.capture()
+        for _ in range(args.warmup):
+            plan.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            plan.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    runs = {}
+    for name, persistent in (("one_workgroup_per_tile", False), ("persistent", True)):
+        plan = BatchPlan.forward(imgs, L, args.wavelet, args.scheme, None, persistent)
+        ms = time_plan(plan)
+        runs[name] = dict(ms=round(ms, 5), gpixel_s=round(plan.pixels / ms / 1e6, 3),
+                          hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          launches_per_level=plan.launches()[1])
+        print(f"[bench] default tiles, {name}: {ms:.4f} ms", file=sys.stderr, flush=True)
+        del plan
+    grid = min(runs, key=lambda k: runs[k]["ms"])
+    print("[bench] tuning tiles per size class", file=sys.stderr, flush=True)
+    class_tiles = autotune.tune(args.wavelet, args.scheme, args.dtype, L, cache_path=None)
+    plan = BatchPlan.forward(imgs, L, args.wavelet, args.scheme, class_tiles,
+                             grid == "persistent")
+    ms_tuned = time_plan(plan)
+    runs["tuned_tiles"] = dict(ms=round(ms_tuned, 5), grid=grid, class_tiles=class_tiles,
+                               gpixel_s=round(plan.pixels / ms_tuned / 1e6, 3),
+                               launches_per_level=plan.launches()[1])
+    best = min(runs.values(), key=lambda r: r["ms"])
+    ms = best["ms"]
     px = plan.pixels
     # spot parity: the largest image against the oracle
     import oracle
@@ -435,11 +458,11 @@ def run_batch_workload(args):
         warmup=args.warmup, ms_per_step=round(ms, 5), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype=args.dtype, data="synthetic",
         config=dict(workload=f"{len(sizes)} images, sides log-uniform in [64, 4096] (multiples "
-                             f"of 32), uniform integers 0..255, {L} levels forward, one captured "
-                             f"graph of batched launches", images=len(sizes), pixels=px,
-                    levels=L, class_tiles=class_tiles),
+                             f"of 32), uniform integers 0..255, {L} levels forward, planned "
+                             f"once, one captured graph", images=len(sizes), pixels=px,
+                    levels=L),
         hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), algorithmic_bytes=alg,
-        max_err_rel_largest_image=err)), flush=True)
+        runs=runs, max_err_rel_largest_image=err)), flush=True)
 
 
 def run_serve_workload(args):

@@ -241,11 +241,23 @@ int dwt2_default_tile(int32_t width, int32_t height, dwt2_wavelet wavelet,
                       dwt2_scheme scheme, dwt2_dtype dtype);
 
 /* ---- batches of images ---------------------------------------------------
- * Many images of one storage type, wavelet, scheme and level count in few
- * launches: each level is one launch per size class and chunk of up to 36
- * images, one workgroup per tile; the images' level parameters travel in the
- * kernel arguments, so a captured HIP graph of the calls holds everything it
- * needs. */
+ * Many images of one storage type, wavelet and level count, planned once and
+ * run as few launches: each level is one launch over every image whose size
+ * class uses the same tile configuration (one launch per level with the
+ * default configurations of FP32 storage). Not a topic of the paper, which
+ * transforms one image at a time: batching serves many uneven images.
+ *
+ * dwt2_batch_plan writes a plan (a byte image in host memory, of
+ * dwt2_batch_plan_bytes bytes): per launch, a tile -> image map and every
+ * image's level parameters, with the images' device pointers. The caller
+ * copies it byte for byte into device memory (e.g. hipMemcpy) and passes both
+ * copies to dwt2_batch_run, which reads the launch shapes from the host copy
+ * while the kernels read the device copy. The launches hold nothing but
+ * pointers into the device copy, so a captured HIP graph of dwt2_batch_run
+ * replays the whole batch. Both copies must stay unchanged while launches
+ * that use them may run, and the device copy must equal the host copy (the
+ * library cannot check device memory; a differing copy gives wrong results or
+ * faults). */
 typedef struct {
     const void *src;        /* forward: image; inverse: Mallat coefficients */
     int64_t src_pitch;      /* elements */
@@ -263,18 +275,39 @@ typedef struct {
  * for sizes below 2. */
 int dwt2_size_class(int32_t width, int32_t height);
 
-/* Batched L-level forward (inverse) DWT of images[0..n). Each image is
+/* Bytes of the plan of an L-level forward (inverse = 0) or inverse
+ * (inverse = 1) transform of images[0..n), n >= 1, in *bytes. Each image is
  * checked as by dwt2_forward (dwt2_inverse); src and dst of one image must
- * not overlap, and no two images may share an output or workspace.
- * class_tiles: NULL for the library's choice, else DWT2_SIZE_CLASSES tile
- * configuration ids, the one used for levels of each class.
- * Returns a dwt2_status; nothing is enqueued if any image is invalid. */
-int dwt2_forward_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
-                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
-                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream);
-int dwt2_inverse_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
-                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
-                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream);
+ * not overlap, and no image may write a buffer another image reads or writes
+ * (images may share a source). class_tiles: NULL for the library's choice,
+ * else DWT2_SIZE_CLASSES tile configuration ids, the one used for the levels
+ * of each size class. Returns a dwt2_status. */
+int dwt2_batch_plan_bytes(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                          dwt2_wavelet wavelet, int32_t levels, int32_t inverse,
+                          dwt2_boundary boundary, const int32_t *class_tiles, size_t *bytes);
+
+/* Writes the plan into plan[0..plan_bytes) (host memory): DWT2_ERR_WORKSPACE
+ * if plan_bytes is too small, else as dwt2_batch_plan_bytes. */
+int dwt2_batch_plan(const dwt2_image *images, int32_t n, dwt2_dtype dtype, dwt2_wavelet wavelet,
+                    int32_t levels, int32_t inverse, dwt2_boundary boundary,
+                    const int32_t *class_tiles, void *plan, size_t plan_bytes);
+
+/* Number of launches of a plan, in total and (per_level: NULL or `levels`
+ * entries) per level, index j for level j+1. */
+int dwt2_batch_launches(const void *plan, size_t plan_bytes, int32_t *launches,
+                        int32_t *per_level);
+
+/* Grid of dwt2_batch_run: one workgroup per tile (flags 0), or
+ * DWT2_BATCH_PERSISTENT: at most as many workgroups as fit on the device at
+ * once, each walking several tiles. Results are identical. */
+#define DWT2_BATCH_PERSISTENT 1
+
+/* Enqueues the planned transform on `stream`: plan (host memory, plan_bytes
+ * bytes as written by dwt2_batch_plan) and plan_device (its device copy).
+ * Launches run level after level in stream order. Returns a dwt2_status;
+ * nothing is enqueued if the host plan is malformed or an argument invalid. */
+int dwt2_batch_run(const void *plan, size_t plan_bytes, const void *plan_device,
+                   dwt2_scheme scheme, int32_t flags, hipStream_t stream);
 
 /* One level of one image, as given to dwt2_forward_level (forward) or
  * dwt2_inverse_level (inverse): `full` is the width x height buffer (the

@@ -1,21 +1,23 @@
-"""Per-size-class choice of the 2-D tile configuration for batched launches.
+"""Per-size-class choice of the tile configuration for planned batches.
 
-For each size class the tuner times every compiled 2-D tile configuration on
-a batch of images of that class (graph-captured, so host overhead does not
-count) and keeps the fastest. Results are cached in a JSON file keyed by
-device, wavelet, scheme, storage type and level count.
+Each size class is tuned on its own: a batch of images whose level input
+lies in that class, transformed by one level, so that only that class's
+configuration is exercised. Every compiled configuration is timed on it
+(graph-captured replays, so host overhead does not count) and the fastest
+kept. Results are cached in a JSON file keyed by device, wavelet, scheme,
+storage type and level count; the level count only keys the cache (a class's
+launches look alike at every level).
 """
 from __future__ import annotations
 
 import json
 import os
 
-from . import _lib, load, tile_configs
-from .batch import BatchPlan
+from . import tile_configs
 
-# Representative level-input sides of the four size classes.
+# Representative level-input sides of the four size classes (<= 128^2,
+# <= 512^2, <= 2048^2, larger).
 CLASS_SIDES = (96, 384, 1536, 4096)
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dwt2_autotune.json")
 
 
 def _time_plan(plan, reps=5):
@@ -34,50 +36,75 @@ def _time_plan(plan, reps=5):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(wavelet="cdf97", scheme="nonseparable", dtype="f32", levels=1, images_per_class=8,
-         cache_path=DEFAULT_CACHE, force=False, verbose=False):
-    """Return the fastest 2-D tile id for each size class (cached)."""
+def gpu_class_timer(wavelet, scheme, dtype, images_per_class=8):
+    """timer(cls, tile) -> ms of a one-level batch of class `cls` images on
+    the current GPU with `tile` for that class."""
     import torch
-    dev = torch.cuda.get_device_name()
-    key = f"{dev}|{wavelet}|{scheme}|{dtype}|L{levels}"
+    from .batch import BatchPlan
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    gen = torch.Generator(device="cuda").manual_seed(12345)
+    cache = {}
+
+    def timer(cls, tile):
+        if cls not in cache:
+            side = CLASS_SIDES[cls]
+            n = images_per_class if side <= 1536 else 2
+            cache.clear()   # keep one class's images alive at a time
+            cache[cls] = [torch.rand(side, side, device="cuda", generator=gen).mul_(255).to(tdt)
+                          for _ in range(n)]
+        class_tiles = [0] * len(CLASS_SIDES)
+        class_tiles[cls] = tile
+        plan = BatchPlan.forward(cache[cls], 1, wavelet, scheme, class_tiles)
+        return _time_plan(plan)
+    return timer
+
+
+def tune(wavelet="cdf97", scheme="nonseparable", dtype="f32", levels=1, cache_path=None,
+         force=False, verbose=False, timer=None, candidates=None, device_name=None):
+    """Return the fastest tile id for each size class.
+
+    cache_path: a JSON file read before and written after tuning (None: no
+    cache). force: re-tune even when the cache holds the key. timer,
+    candidates, device_name: the per-(class, tile) timer, the tile ids to try
+    and the device name of the cache key; by default the current GPU, every
+    compiled configuration and that GPU's name."""
+    if device_name is None:
+        import torch
+        device_name = torch.cuda.get_device_name()
+    key = f"{device_name}|{wavelet}|{scheme}|{dtype}|L{levels}"
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
-            cache = json.load(open(cache_path))
+            with open(cache_path) as f:
+                cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
     if not force and key in cache:
         return list(cache[key]["class_tiles"])
-    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
-    cands = [c[0] for c in tile_configs(wavelet)]
+    if candidates is None:
+        candidates = [c[0] for c in tile_configs(wavelet)]
+    if timer is None:
+        timer = gpu_class_timer(wavelet, scheme, dtype)
     best, timings = [], {}
-    gen = torch.Generator(device="cuda").manual_seed(12345)
-    for c, side in enumerate(CLASS_SIDES):
-        side -= side % (1 << levels)
-        n = images_per_class if side <= 1536 else 2
-        imgs = [torch.rand(side, side, device="cuda", generator=gen).mul_(255).to(tdt)
-                for _ in range(n)]
-        res = {}
-        for t in cands:
-            class_tiles = [t] * _lib.SIZE_CLASSES
-            plan = BatchPlan.forward(imgs, levels, wavelet, scheme, class_tiles)
-            res[t] = _time_plan(plan)
-            del plan
+    for cls in range(len(CLASS_SIDES)):
+        res = {t: float(timer(cls, t)) for t in candidates}
         pick = min(res, key=res.get)
         best.append(pick)
-        timings[str(c)] = {str(t): round(v, 5) for t, v in res.items()}
+        timings[str(cls)] = {str(t): round(v, 5) for t, v in res.items()}
         if verbose:
-            print(f"class {c} (side {side}): " +
+            print(f"class {cls} (side {CLASS_SIDES[cls]}): " +
                   ", ".join(f"tile {t} {v * 1000:.1f} us" for t, v in res.items()) +
                   f" -> {pick}", flush=True)
-        del imgs
     cache[key] = {"class_tiles": best, "ms": timings}
     if cache_path:
-        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        d = os.path.dirname(cache_path)
+        if d:
+            os.makedirs(d, exist_ok=True)
         tmp = cache_path + ".tmp"
-        json.dump(cache, open(tmp, "w"), indent=1)
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
         os.replace(tmp, cache_path)
     return best
 
 
-__all__ = ["tune", "CLASS_SIDES", "load"]
+__all__ = ["tune", "CLASS_SIDES", "gpu_class_timer"]

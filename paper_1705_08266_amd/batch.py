@@ -1,14 +1,16 @@
-"""Batches of uneven images: one launch per level and size class, captured
-as one HIP graph.
+"""Batches of uneven images, planned once and run as one launch per level
+(per tile configuration in use), capturable as one HIP graph.
 
     plan = BatchPlan.forward(images, levels=3)     # list of 2-D GPU tensors
-    plan.capture()                                 # record the whole chain once
+    plan.capture()                                 # record the launches once
     plan.replay()                                  # one graph launch per call
     coefs = plan.outputs
 
-Every transform step runs in the library's batched kernels
-(dwt2_forward_batch / dwt2_inverse_batch); this module allocates outputs and
-workspaces with PyTorch and marshals descriptors.
+The library plans the launch table (dwt2_batch_plan) in host memory; this
+module copies it to a device tensor and hands both copies to dwt2_batch_run,
+whose kernels read the per-tile image map and level parameters from device
+memory. Every transform step runs in the library's kernels; this module
+allocates outputs, workspaces and the plan's device copy with PyTorch.
 """
 from __future__ import annotations
 
@@ -44,13 +46,12 @@ def _class_tiles(class_tiles):
     return (ctypes.c_int32 * _lib.SIZE_CLASSES)(*[int(t) for t in class_tiles])
 
 
-def run_batch(srcs, dsts, workspaces, inverse=False, wavelet="cdf97", levels=1,
-              scheme="nonseparable", class_tiles=None, stream=None):
-    """Enqueue one batched transform of srcs[i] -> dsts[i]."""
-    if not (len(srcs) == len(dsts) == len(workspaces)):
-        raise ValueError("srcs, dsts and workspaces must have the same length")
-    if not srcs:
-        return
+def make_plan(srcs, dsts, workspaces, inverse=False, wavelet="cdf97", levels=1,
+              class_tiles=None):
+    """The host plan of a batched transform srcs[i] -> dsts[i] (a ctypes byte
+    buffer)."""
+    if not (len(srcs) == len(dsts) == len(workspaces)) or not srcs:
+        raise ValueError("need one dst and one workspace per src, and at least one image")
     dt = _dtype_code(srcs[0])
     for s, d in zip(srcs, dsts):
         if not (s.is_cuda and d.is_cuda) or s.dim() != 2 or s.stride(1) != 1 or d.stride(1) != 1:
@@ -58,39 +59,62 @@ def run_batch(srcs, dsts, workspaces, inverse=False, wavelet="cdf97", levels=1,
         if _dtype_code(s) != dt or _dtype_code(d) != dt or s.shape != d.shape:
             raise ValueError("all batch images share one dtype; dst matches src")
     arr = _image_array(srcs, dsts, workspaces)
-    fn = load().dwt2_inverse_batch if inverse else load().dwt2_forward_batch
-    st = fn(arr, len(srcs), dt, _wavelet(wavelet), int(levels), _lib.EXT_WHOLE_SAMPLE_SYMMETRIC,
-            _scheme(scheme), _class_tiles(class_tiles), _stream_ptr(stream))
-    _lib.check(st, "dwt2_inverse_batch" if inverse else "dwt2_forward_batch")
+    lib = load()
+    args = (arr, len(srcs), dt, _wavelet(wavelet), int(levels), int(bool(inverse)),
+            _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _class_tiles(class_tiles))
+    n = ctypes.c_size_t()
+    _lib.check(lib.dwt2_batch_plan_bytes(*args, ctypes.byref(n)), "dwt2_batch_plan_bytes")
+    buf = (ctypes.c_ubyte * n.value)()
+    _lib.check(lib.dwt2_batch_plan(*args, buf, n.value), "dwt2_batch_plan")
+    return buf
 
 
 class BatchPlan:
-    """A fixed batch of images with its outputs and workspaces allocated once;
-    the batched launches can be captured in a HIP graph and replayed."""
+    """A fixed batch of images with outputs, workspaces and the plan's device
+    copy allocated once; run() enqueues it, capture()/replay() use a graph."""
 
-    def __init__(self, srcs, inverse, wavelet, levels, scheme, class_tiles):
+    def __init__(self, srcs, inverse, wavelet, levels, scheme, class_tiles, persistent=False):
         import torch
         self.srcs = list(srcs)
         self.inverse = inverse
         self.wavelet, self.levels, self.scheme = wavelet, levels, scheme
         self.class_tiles = class_tiles
+        self.persistent = persistent
         self.outputs = [torch.empty_like(s) for s in self.srcs]
         self.workspaces = [
             torch.empty(max(1, workspace_bytes(s.shape[1], s.shape[0], levels) // 4),
                         dtype=torch.float32, device=s.device) for s in self.srcs]
+        self.host_plan = make_plan(self.srcs, self.outputs, self.workspaces, inverse, wavelet,
+                                   levels, class_tiles)
+        host = torch.frombuffer(bytearray(self.host_plan), dtype=torch.uint8)
+        self.device_plan = host.to(self.srcs[0].device)
+        torch.cuda.synchronize()
         self.graph = None
 
     @classmethod
-    def forward(cls, images, levels=1, wavelet="cdf97", scheme="nonseparable", class_tiles=None):
-        return cls(images, False, wavelet, levels, scheme, class_tiles)
+    def forward(cls, images, levels=1, wavelet="cdf97", scheme="nonseparable", class_tiles=None,
+                persistent=False):
+        return cls(images, False, wavelet, levels, scheme, class_tiles, persistent)
 
     @classmethod
-    def inverse_of(cls, coefs, levels=1, wavelet="cdf97", scheme="nonseparable", class_tiles=None):
-        return cls(coefs, True, wavelet, levels, scheme, class_tiles)
+    def inverse_of(cls, coefs, levels=1, wavelet="cdf97", scheme="nonseparable",
+                   class_tiles=None, persistent=False):
+        return cls(coefs, True, wavelet, levels, scheme, class_tiles, persistent)
+
+    def launches(self):
+        """(total launches, launches per level j = 1..L)."""
+        total = ctypes.c_int32()
+        per = (ctypes.c_int32 * self.levels)()
+        _lib.check(load().dwt2_batch_launches(self.host_plan, len(self.host_plan),
+                                              ctypes.byref(total), per), "dwt2_batch_launches")
+        return total.value, list(per)
 
     def run(self, stream=None):
-        run_batch(self.srcs, self.outputs, self.workspaces, self.inverse, self.wavelet,
-                  self.levels, self.scheme, self.class_tiles, stream)
+        st = load().dwt2_batch_run(self.host_plan, len(self.host_plan),
+                                   self.device_plan.data_ptr(), _scheme(self.scheme),
+                                   _lib.BATCH_PERSISTENT if self.persistent else 0,
+                                   _stream_ptr(stream))
+        _lib.check(st, "dwt2_batch_run")
 
     def capture(self):
         import torch

@@ -442,30 +442,187 @@ bool batch_images_conflict(const dwt2_image *images, int n, int dtype, int level
     return cross_conflict(v);
 }
 
-// Launch one level of many images: group by size class, then launch the
-// class's tile configuration over chunks of at most kBatchMax images.
-template <typename Batch, typename Params, typename Launch>
-int launch_batch_level(const Params *params, const int *tiles_of, const int *cls, int n,
-                       Launch launch) {
+// ---- planned batches ---------------------------------------------------------
+// A plan is one byte image, valid both on the host (read by dwt2_batch_run for
+// the launch shapes) and, copied, in device memory (read by the kernels): a
+// header, one PlanLaunch per launch, then per launch the tile -> image map,
+// each image's first tile and the images' level parameters. Offsets are from
+// the start of the plan; sections are 256-byte aligned.
+constexpr uint32_t kPlanMagic = 0x42545744u;   // "DWTB"
+constexpr int32_t kPlanVersion = 1;
+
+struct PlanHeader {
+    uint32_t magic;
+    int32_t version;
+    int32_t n, levels, inverse, dtype, wavelet, nlaunch;
+    uint64_t bytes;
+};
+struct PlanLaunch {
+    int32_t level;          // 1-based
+    int32_t tile;           // tile configuration
+    int32_t f32_a, f32_b;   // operand types, as indexed in the single-level tables
+    int32_t images;         // images in this launch
+    int32_t total;          // tiles in this launch
+    uint64_t off_img, off_start, off_params;
+};
+
+const PlanLaunch *plan_launches(const PlanHeader *h) {
+    return reinterpret_cast<const PlanLaunch *>(reinterpret_cast<const char *>(h) +
+                                                sizeof(PlanHeader));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+const FwdTableTable &fwd_plan_table(int dt) {
+    return dt == DWT2_F32 ? kFwdPlanF32 : dt == DWT2_F16 ? kFwdPlanF16 : kFwdPlanBF16;
+}
+const InvTableTable &inv_plan_table(int dt) {
+    return dt == DWT2_F32 ? kInvPlanF32 : dt == DWT2_F16 ? kInvPlanF16 : kInvPlanBF16;
+}
+
+// Structural checks of a host plan before its launches are read.
+int check_plan(const void *plan, size_t bytes, const PlanHeader **out) {
+    if (!plan || bytes < sizeof(PlanHeader)) return DWT2_ERR_INVALID_ARG;
+    const PlanHeader *h = static_cast<const PlanHeader *>(plan);
+    if (h->magic != kPlanMagic || h->version != kPlanVersion || h->bytes != bytes)
+        return DWT2_ERR_INVALID_ARG;
+    if (!valid_dtype(h->dtype) || !valid_wavelet(h->wavelet) || h->levels < 1 ||
+        h->levels > 16 || h->nlaunch < 0 || h->n < 0)
+        return DWT2_ERR_INVALID_ARG;
+    if (sizeof(PlanHeader) + (size_t)h->nlaunch * sizeof(PlanLaunch) > bytes)
+        return DWT2_ERR_INVALID_ARG;
+    const PlanLaunch *L = plan_launches(h);
+    const size_t psize = h->inverse ? sizeof(InvParams) : sizeof(FwdParams);
+    for (int k = 0; k < h->nlaunch; ++k) {
+        const PlanLaunch &l = L[k];
+        if (l.level < 1 || l.level > h->levels || l.tile < 0 || l.tile >= kNumTiles ||
+            (l.f32_a | l.f32_b) & ~1 || l.images < 1 || l.images > h->n || l.total < 1)
+            return DWT2_ERR_INVALID_ARG;
+        if (l.off_img + 4 * (uint64_t)l.total > bytes ||
+            l.off_start + 4 * (uint64_t)l.images > bytes ||
+            l.off_params + psize * (uint64_t)l.images > bytes)
+            return DWT2_ERR_INVALID_ARG;
+    }
+    *out = h;
+    return DWT2_OK;
+}
+
+// Plans an L-level batched transform: for each level (forward 1..L, inverse
+// L..1) and each tile configuration its images' size classes use, one launch.
+int build_plan(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
+               int32_t levels, int32_t inverse, int32_t boundary, const int32_t *class_tiles,
+               std::vector<unsigned char> &out) {
+    if (n < 1 || !images) return DWT2_ERR_INVALID_ARG;
+    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) ||
+        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC || (inverse != 0 && inverse != 1))
+        return DWT2_ERR_UNSUPPORTED;
+    if (levels < 1 || levels > 16) return DWT2_ERR_INVALID_ARG;
+    int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        Batch b;
-        b.n = 0;
-        b.tile_start[0] = 0;
-        int tile = -1;
-        for (int i = 0; i <= n; ++i) {
-            const bool take = i < n && cls[i] == c;
-            if (take) {
-                tile = tiles_of[i];
-                b.p[b.n] = params[i];
-                b.tile_start[b.n + 1] = b.tile_start[b.n] + params[i].tiles_x * params[i].tiles_y;
-                ++b.n;
+        ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
+        if (ctile[c] < 0 || ctile[c] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int st = check_batch_image(images[i], dtype, levels);
+        if (st) return st;
+    }
+    if (batch_images_conflict(images, n, dtype, levels)) return DWT2_ERR_INVALID_ARG;
+
+    const size_t es = elem_size(dtype);
+    struct Group {
+        PlanLaunch l;
+        std::vector<int32_t> img, start;
+        std::vector<FwdParams> fp;
+        std::vector<InvParams> ip;
+    };
+    std::vector<Group> groups;
+    for (int step = 0; step < levels; ++step) {
+        const int j = inverse ? levels - step : step + 1;
+        const int first = (int)groups.size();
+        for (int i = 0; i < n; ++i) {
+            const dwt2_image &im = images[i];
+            const int W = im.width, H = im.height;
+            const int w = W >> (j - 1), h = H >> (j - 1);
+            const int tile = ctile[size_class(w, h)];
+            int g = first;
+            while (g < (int)groups.size() && groups[g].l.tile != tile) ++g;
+            if (g == (int)groups.size()) {
+                Group ng;
+                ng.l = PlanLaunch{};
+                ng.l.level = j;
+                ng.l.tile = tile;
+                if (inverse) {
+                    ng.l.f32_a = j == levels ? dtype == DWT2_F32 : 1;   // LL input
+                    ng.l.f32_b = j == 1 ? dtype == DWT2_F32 : 1;        // level output
+                } else {
+                    ng.l.f32_a = j == 1 ? dtype == DWT2_F32 : 1;        // level input
+                    ng.l.f32_b = j == levels ? dtype == DWT2_F32 : 1;   // LL output
+                }
+                groups.push_back(ng);
             }
-            if (b.n > 0 && (b.n == kBatchMax || i == n)) {
-                const int st = launch(b, tile);
-                if (st) return st;
-                b.n = 0;
+            Group &G = groups[g];
+            float *ws0 = static_cast<float *>(im.workspace);
+            float *ws[2] = {ws0, ws0 ? ws0 + (size_t)(W / 2) * (H / 2) : nullptr};
+            int tiles;
+            if (inverse) {
+                const char *cbase = static_cast<const char *>(im.src);
+                const int64_t cp = im.src_pitch;
+                const void *ll = j == levels ? im.src : (const void *)ws[(j - 1) & 1];
+                const InvParams p = inv_params(
+                    ll, j == levels ? cp : w / 2, j == levels ? dtype : DWT2_F32,
+                    cbase + (size_t)(w / 2) * es, cbase + (size_t)((int64_t)(h / 2) * cp) * es,
+                    cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es, cp, dtype,
+                    j == 1 ? im.dst : (void *)ws[(j - 2) & 1], j == 1 ? im.dst_pitch : w,
+                    j == 1 ? dtype : DWT2_F32, w, h, wavelet, tile);
+                tiles = p.tiles_x * p.tiles_y;
+                G.ip.push_back(p);
+            } else {
+                char *cbase = static_cast<char *>(im.dst);
+                const int64_t cp = im.dst_pitch;
+                const FwdParams p = fwd_params(
+                    j == 1 ? im.src : (const void *)ws[(j - 2) & 1], j == 1 ? im.src_pitch : w,
+                    j == 1 ? dtype : DWT2_F32, w, h,
+                    j == levels ? im.dst : (void *)ws[(j - 1) & 1], j == levels ? cp : w / 2,
+                    j == levels ? dtype : DWT2_F32, cbase + (size_t)(w / 2) * es,
+                    cbase + (size_t)((int64_t)(h / 2) * cp) * es,
+                    cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es, cp, dtype, wavelet,
+                    tile);
+                tiles = p.tiles_x * p.tiles_y;
+                G.fp.push_back(p);
             }
+            const int local = (int)G.start.size();
+            G.start.push_back((int32_t)G.img.size());
+            if ((int64_t)G.img.size() + tiles > (int64_t)INT32_MAX) return DWT2_ERR_INVALID_ARG;
+            G.img.insert(G.img.end(), (size_t)tiles, (int32_t)local);
         }
+    }
+    // lay out: header, launches, then per launch its three arrays
+    size_t off = align256(sizeof(PlanHeader) + groups.size() * sizeof(PlanLaunch));
+    for (Group &G : groups) {
+        G.l.images = (int32_t)G.start.size();
+        G.l.total = (int32_t)G.img.size();
+        G.l.off_img = off;
+        off = align256(off + 4 * G.img.size());
+        G.l.off_start = off;
+        off = align256(off + 4 * G.start.size());
+        G.l.off_params = off;
+        off = align256(off + (inverse ? sizeof(InvParams) * G.ip.size()
+                                      : sizeof(FwdParams) * G.fp.size()));
+    }
+    out.assign(off, 0);
+    PlanHeader h{kPlanMagic, kPlanVersion, n, levels, inverse, dtype, wavelet,
+                 (int32_t)groups.size(), (uint64_t)off};
+    std::memcpy(out.data(), &h, sizeof h);
+    for (size_t k = 0; k < groups.size(); ++k) {
+        const Group &G = groups[k];
+        std::memcpy(out.data() + sizeof(PlanHeader) + k * sizeof(PlanLaunch), &G.l,
+                    sizeof(PlanLaunch));
+        std::memcpy(out.data() + G.l.off_img, G.img.data(), 4 * G.img.size());
+        std::memcpy(out.data() + G.l.off_start, G.start.data(), 4 * G.start.size());
+        if (inverse)
+            std::memcpy(out.data() + G.l.off_params, G.ip.data(), sizeof(InvParams) * G.ip.size());
+        else
+            std::memcpy(out.data() + G.l.off_params, G.fp.data(), sizeof(FwdParams) * G.fp.size());
     }
     return DWT2_OK;
 }
@@ -763,118 +920,76 @@ int dwt2_size_class(int32_t width, int32_t height) {
     return size_class(width, height);
 }
 
-int dwt2_forward_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
-                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
-                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
-    if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
-    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
-        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
-        return DWT2_ERR_UNSUPPORTED;
-    int ctile[DWT2_SIZE_CLASSES];
-    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
-        if (ctile[c] < 0 || ctile[c] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
-    }
-    for (int i = 0; i < n; ++i) {
-        const int st = check_batch_image(images[i], dtype, levels);
-        if (st) return st;
-    }
-    if (batch_images_conflict(images, n, dtype, levels)) return DWT2_ERR_INVALID_ARG;
-    const hipStream_t s = stream;
-    const size_t es = elem_size(dtype);
-    std::vector<FwdParams> params_v(n > 0 ? n : 1);
-    std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
-    FwdParams *params = params_v.data();
-    int *cls = cls_v.data();
-    int *tiles = tiles_v.data();
-    int st = DWT2_OK;
-    for (int j = 1; j <= levels && st == DWT2_OK; ++j) {
-        for (int i = 0; i < n; ++i) {
-            const dwt2_image &im = images[i];
-            const int W = im.width, H = im.height;
-            const int w = W >> (j - 1), h = H >> (j - 1);
-            float *ws0 = static_cast<float *>(im.workspace);
-            float *ws[2] = {ws0, ws0 ? ws0 + (size_t)(W / 2) * (H / 2) : nullptr};
-            char *cbase = static_cast<char *>(im.dst);
-            const int64_t cp = im.dst_pitch;
-            const void *in = j == 1 ? im.src : (const void *)ws[(j - 2) & 1];
-            const int64_t in_pitch = j == 1 ? im.src_pitch : w;
-            void *hl = cbase + (size_t)(w / 2) * es;
-            void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
-            void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
-            void *ll = j == levels ? im.dst : (void *)ws[(j - 1) & 1];
-            const int64_t ll_pitch = j == levels ? cp : w / 2;
-            cls[i] = size_class(w, h);
-            tiles[i] = ctile[cls[i]];
-            params[i] = fwd_params(in, in_pitch, j == 1 ? dtype : DWT2_F32, w, h, ll, ll_pitch,
-                                   j == levels ? dtype : DWT2_F32, hl, lh, hh, cp, dtype, wavelet,
-                                   tiles[i]);
-        }
-        const int in_f32 = j == 1 ? dtype == DWT2_F32 : 1;
-        const int ll_f32 = j == levels ? dtype == DWT2_F32 : 1;
-        st = launch_batch_level<FwdBatch>(params, tiles, cls, n, [&](const FwdBatch &b, int tile) {
-            const hipError_t e = fwd_batch_table(dtype)[wavelet][scheme][in_f32][ll_f32][tile](b, s);
-            return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
-        });
-    }
-    return st;
+int dwt2_batch_plan_bytes(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
+                          dwt2_wavelet wavelet, int32_t levels, int32_t inverse,
+                          dwt2_boundary boundary, const int32_t *class_tiles, size_t *bytes) {
+    if (!bytes) return DWT2_ERR_INVALID_ARG;
+    std::vector<unsigned char> plan;
+    const int st = build_plan(images, n, dtype, wavelet, levels, inverse, boundary, class_tiles,
+                              plan);
+    if (st) return st;
+    *bytes = plan.size();
+    return DWT2_OK;
 }
 
-int dwt2_inverse_batch(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
-                       dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
-                       dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
-    if (n < 0 || (n > 0 && !images)) return DWT2_ERR_INVALID_ARG;
-    if (!valid_dtype(dtype) || !valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme) ||
-        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC)
-        return DWT2_ERR_UNSUPPORTED;
-    int ctile[DWT2_SIZE_CLASSES];
-    for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
-        ctile[c] = class_tiles ? class_tiles[c] : class_tile(c, dtype);
-        if (ctile[c] < 0 || ctile[c] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
+int dwt2_batch_plan(const dwt2_image *images, int32_t n, dwt2_dtype dtype, dwt2_wavelet wavelet,
+                    int32_t levels, int32_t inverse, dwt2_boundary boundary,
+                    const int32_t *class_tiles, void *plan, size_t plan_bytes) {
+    if (!plan) return DWT2_ERR_INVALID_ARG;
+    std::vector<unsigned char> v;
+    const int st = build_plan(images, n, dtype, wavelet, levels, inverse, boundary, class_tiles, v);
+    if (st) return st;
+    if (plan_bytes < v.size()) return DWT2_ERR_WORKSPACE;
+    std::memcpy(plan, v.data(), v.size());
+    return DWT2_OK;
+}
+
+int dwt2_batch_launches(const void *plan, size_t plan_bytes, int32_t *launches,
+                        int32_t *per_level) {
+    const PlanHeader *h = nullptr;
+    const int st = check_plan(plan, plan_bytes, &h);
+    if (st) return st;
+    if (launches) *launches = h->nlaunch;
+    if (per_level) {
+        for (int j = 0; j < h->levels; ++j) per_level[j] = 0;
+        const PlanLaunch *L = plan_launches(h);
+        for (int k = 0; k < h->nlaunch; ++k) ++per_level[L[k].level - 1];
     }
-    for (int i = 0; i < n; ++i) {
-        const int st = check_batch_image(images[i], dtype, levels);
-        if (st) return st;
-    }
-    if (batch_images_conflict(images, n, dtype, levels)) return DWT2_ERR_INVALID_ARG;
-    const hipStream_t s = stream;
-    const size_t es = elem_size(dtype);
-    std::vector<InvParams> params_v(n > 0 ? n : 1);
-    std::vector<int> cls_v(n > 0 ? n : 1), tiles_v(n > 0 ? n : 1);
-    InvParams *params = params_v.data();
-    int *cls = cls_v.data();
-    int *tiles = tiles_v.data();
-    int st = DWT2_OK;
-    for (int j = levels; j >= 1 && st == DWT2_OK; --j) {
-        for (int i = 0; i < n; ++i) {
-            const dwt2_image &im = images[i];
-            const int W = im.width, H = im.height;
-            const int w = W >> (j - 1), h = H >> (j - 1);
-            float *ws0 = static_cast<float *>(im.workspace);
-            float *ws[2] = {ws0, ws0 ? ws0 + (size_t)(W / 2) * (H / 2) : nullptr};
-            const char *cbase = static_cast<const char *>(im.src);
-            const int64_t cp = im.src_pitch;
-            const void *ll = j == levels ? im.src : (const void *)ws[(j - 1) & 1];
-            const int64_t ll_pitch = j == levels ? cp : w / 2;
-            const void *hl = cbase + (size_t)(w / 2) * es;
-            const void *lh = cbase + (size_t)((int64_t)(h / 2) * cp) * es;
-            const void *hh = cbase + (size_t)((int64_t)(h / 2) * cp + w / 2) * es;
-            void *out = j == 1 ? im.dst : (void *)ws[(j - 2) & 1];
-            const int64_t out_pitch = j == 1 ? im.dst_pitch : w;
-            cls[i] = size_class(w, h);
-            tiles[i] = ctile[cls[i]];
-            params[i] = inv_params(ll, ll_pitch, j == levels ? dtype : DWT2_F32, hl, lh, hh, cp,
-                                   dtype, out, out_pitch, j == 1 ? dtype : DWT2_F32, w, h,
-                                   wavelet, tiles[i]);
+    return DWT2_OK;
+}
+
+int dwt2_batch_run(const void *plan, size_t plan_bytes, const void *plan_device,
+                   dwt2_scheme scheme, int32_t flags, hipStream_t stream) {
+    const PlanHeader *h = nullptr;
+    int st = check_plan(plan, plan_bytes, &h);
+    if (st) return st;
+    if (!plan_device) return DWT2_ERR_INVALID_ARG;
+    if (!valid_scheme(scheme) || lds_scheme(scheme)) return DWT2_ERR_UNSUPPORTED;
+    if (flags & ~DWT2_BATCH_PERSISTENT) return DWT2_ERR_UNSUPPORTED;
+    const bool persistent = (flags & DWT2_BATCH_PERSISTENT) != 0;
+    const char *dev = static_cast<const char *>(plan_device);
+    const PlanLaunch *L = plan_launches(h);
+    for (int k = 0; k < h->nlaunch; ++k) {
+        const PlanLaunch &l = L[k];
+        hipError_t e;
+        if (h->inverse) {
+            TableLaunch<InvParams> tl{reinterpret_cast<const int32_t *>(dev + l.off_img),
+                                      reinterpret_cast<const int32_t *>(dev + l.off_start),
+                                      reinterpret_cast<const InvParams *>(dev + l.off_params),
+                                      l.total};
+            e = inv_plan_table(h->dtype)[h->wavelet][scheme][l.f32_a][l.f32_b][l.tile](
+                tl, persistent, stream);
+        } else {
+            TableLaunch<FwdParams> tl{reinterpret_cast<const int32_t *>(dev + l.off_img),
+                                      reinterpret_cast<const int32_t *>(dev + l.off_start),
+                                      reinterpret_cast<const FwdParams *>(dev + l.off_params),
+                                      l.total};
+            e = fwd_plan_table(h->dtype)[h->wavelet][scheme][l.f32_a][l.f32_b][l.tile](
+                tl, persistent, stream);
         }
-        const int ll_f32 = j == levels ? dtype == DWT2_F32 : 1;
-        const int out_f32 = j == 1 ? dtype == DWT2_F32 : 1;
-        st = launch_batch_level<InvBatch>(params, tiles, cls, n, [&](const InvBatch &b, int tile) {
-            const hipError_t e = inv_batch_table(dtype)[wavelet][scheme][ll_f32][out_f32][tile](b, s);
-            return e == hipSuccess ? (int)DWT2_OK : hip_fail(e);
-        });
+        if (e != hipSuccess) return hip_fail(e);
     }
-    return st;
+    return DWT2_OK;
 }
 
 }  // extern "C"

@@ -434,11 +434,12 @@ __global__ __launch_bounds__(64 * WAVES) void inv_level_kernel(InvParams prm) {
     inv_tile<WV, SCH, QPL, ROWS, WAVES, TLL, TB, TOUT>(prm, block_tile(), box, lane, wave);
 }
 
-// ---- batches of images ------------------------------------------------------------
-// Up to kBatchMax images of one size class per launch; their level parameters
-// travel in the kernel arguments (so a captured graph holds them), and
-// tile_start[i] is the first global tile index of image i (tile_start[n] is
-// the total). A persistent grid strides over the tiles of all images.
+// ---- single levels of many images, parameters in the kernel arguments -----------
+// Up to kBatchMax level jobs of one size class per launch (continuous
+// batching: a different set of jobs every call, so nothing is planned ahead);
+// their level parameters travel in the kernel arguments, and tile_start[i] is
+// the first global tile index of job i (tile_start[n] is the total). One
+// workgroup per tile.
 constexpr int kBatchMax = 36;
 
 struct FwdBatch {
@@ -487,6 +488,47 @@ __global__ __launch_bounds__(64 * WAVES) void inv_batch_kernel(InvBatch bt) {
         const int i = batch_image(bt, t);
         inv_tile<WV, SCH, QPL, ROWS, WAVES, TLL, TB, TOUT>(bt.p[i], t - bt.tile_start[i], box, lane,
                                                            wave);
+    }
+}
+
+// ---- batches planned in a device table ------------------------------------------
+// One launch covers every image of one level that uses one tile configuration,
+// however many: the per-image level parameters and a tile -> image map sit in
+// a table in device memory that the host planned once (a graph captures only
+// the launches). Global tile t belongs to image img[t] and is that image's
+// tile t - start[img[t]].
+template <typename P>
+struct TableLaunch {
+    const int32_t *img;     // [total] image of each tile (index into params)
+    const int32_t *start;   // [images] first global tile of each image
+    const P *params;        // [images]
+    int32_t total;          // tiles of the launch
+};
+
+// Every workgroup walks the tiles t = its id, id + gridDim.x, ... below
+// `total`: one tile each when the grid has one workgroup per tile, several
+// when the grid is capped at the resident workgroups (persistent).
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES) void fwd_table_kernel(TableLaunch<FwdParams> tl) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int t = block_tile(); t < tl.total; t += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(tl.img[t]);
+        const FwdParams prm = tl.params[i];
+        fwd_tile<WV, SCH, QPL, ROWS, WAVES, TIN, TLL, TB>(prm, t - tl.start[i], box, lane, wave);
+    }
+}
+
+template <int WV, int SCH, int QPL, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES) void inv_table_kernel(TableLaunch<InvParams> tl) {
+    __shared__ Mailbox<QPL, WAVES> box;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int t = block_tile(); t < tl.total; t += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(tl.img[t]);
+        const InvParams prm = tl.params[i];
+        inv_tile<WV, SCH, QPL, ROWS, WAVES, TLL, TB, TOUT>(prm, t - tl.start[i], box, lane, wave);
     }
 }
 

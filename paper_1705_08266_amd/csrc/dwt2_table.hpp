@@ -47,49 +47,102 @@ hipError_t launch_inv(const InvParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Batches (2-D tile configurations only). With kBatchPersistent a grid of at
-// most the resident number of workgroups strides over the tiles of all
-// images; otherwise one workgroup per tile (the hardware dispatcher balances
-// the load, which measured faster).
-constexpr bool kBatchPersistent = false;
+// Level jobs with parameters in the kernel arguments: one workgroup per tile.
 using FwdBatchLauncher = hipError_t (*)(const FwdBatch &, hipStream_t);
 using InvBatchLauncher = hipError_t (*)(const InvBatch &, hipStream_t);
-
-// Workgroups of `kernel` that fit on the current device at once.
-int resident_blocks(const void *kernel, int block_threads);
 
 template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
 hipError_t launch_fwd_batch(const FwdBatch &b, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    {
-        const auto k = fwd_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>;
-        const int total = b.tile_start[b.n];
-        int grid = total;
-        if constexpr (kBatchPersistent) {
-            static const int resident = resident_blocks((const void *)k, 64 * c.waves);
-            grid = total < resident ? total : resident;
-        }
-        if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
-        return hipGetLastError();
-    }
+    const int total = b.tile_start[b.n];
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fwd_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>),
+                       dim3(total), dim3(64 * c.waves), 0, s, b);
+    return hipGetLastError();
 }
 
 template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
 hipError_t launch_inv_batch(const InvBatch &b, hipStream_t s) {
     constexpr TileCfg c = kTiles[T];
-    {
-        const auto k = inv_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>;
-        const int total = b.tile_start[b.n];
-        int grid = total;
-        if constexpr (kBatchPersistent) {
-            static const int resident = resident_blocks((const void *)k, 64 * c.waves);
-            grid = total < resident ? total : resident;
-        }
-        if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, b);
-        return hipGetLastError();
+    const int total = b.tile_start[b.n];
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((inv_batch_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>),
+                       dim3(total), dim3(64 * c.waves), 0, s, b);
+    return hipGetLastError();
+}
+
+// Workgroups of `kernel` that fit on the current device at once.
+int resident_blocks(const void *kernel, int block_threads);
+
+// Planned batches: one launch over a device table. `persistent` caps the grid
+// at the workgroups that fit on the device at once (each then walks several
+// tiles); otherwise the grid has one workgroup per tile.
+using FwdTableLauncher = hipError_t (*)(const TableLaunch<FwdParams> &, bool, hipStream_t);
+using InvTableLauncher = hipError_t (*)(const TableLaunch<InvParams> &, bool, hipStream_t);
+
+template <int WV, int SCH, int T, typename TIN, typename TLL, typename TB>
+hipError_t launch_fwd_table(const TableLaunch<FwdParams> &tl, bool persistent, hipStream_t s) {
+    constexpr TileCfg c = kTiles[T];
+    const auto k = fwd_table_kernel<WV, SCH, c.qpl, c.rows, c.waves, TIN, TLL, TB>;
+    int grid = tl.total;
+    if (persistent) {
+        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+        grid = grid < resident ? grid : resident;
     }
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, tl);
+    return hipGetLastError();
+}
+
+template <int WV, int SCH, int T, typename TLL, typename TB, typename TOUT>
+hipError_t launch_inv_table(const TableLaunch<InvParams> &tl, bool persistent, hipStream_t s) {
+    constexpr TileCfg c = kTiles[T];
+    const auto k = inv_table_kernel<WV, SCH, c.qpl, c.rows, c.waves, TLL, TB, TOUT>;
+    int grid = tl.total;
+    if (persistent) {
+        static const int resident = resident_blocks((const void *)k, 64 * c.waves);
+        grid = grid < resident ? grid : resident;
+    }
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * c.waves), 0, s, tl);
+    return hipGetLastError();
+}
+
+template <int WV, int SCH, typename TIN, typename TLL, typename TB, int... I>
+constexpr std::array<FwdTableLauncher, kNumTiles> fwd_table_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_fwd_table<WV, SCH, I, TIN, TLL, TB>...};
+}
+template <int WV, int SCH, typename TLL, typename TB, typename TOUT, int... I>
+constexpr std::array<InvTableLauncher, kNumTiles> inv_table_tiles(std::integer_sequence<int, I...>) {
+    return {&launch_inv_table<WV, SCH, I, TLL, TB, TOUT>...};
+}
+
+// Index [wavelet][scheme][first operand is FP32][second operand is FP32]
+// [config], as for the single-level tables.
+using FwdTableTable = std::array<std::array<std::array<std::array<std::array<FwdTableLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
+using InvTableTable = std::array<std::array<std::array<std::array<std::array<InvTableLauncher, kNumTiles>, 2>, 2>, 2>, 2>;
+
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<std::array<FwdTableLauncher, kNumTiles>, 2>, 2> fwd_table_types() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{fwd_table_tiles<WV, SCH, T, T, T>(S{}), fwd_table_tiles<WV, SCH, T, float, T>(S{})},
+             {fwd_table_tiles<WV, SCH, float, T, T>(S{}), fwd_table_tiles<WV, SCH, float, float, T>(S{})}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<std::array<InvTableLauncher, kNumTiles>, 2>, 2> inv_table_types() {
+    using S = std::make_integer_sequence<int, kNumTiles>;
+    return {{{inv_table_tiles<WV, SCH, T, T, T>(S{}), inv_table_tiles<WV, SCH, T, T, float>(S{})},
+             {inv_table_tiles<WV, SCH, float, T, T>(S{}), inv_table_tiles<WV, SCH, float, T, float>(S{})}}};
+}
+template <typename T>
+constexpr FwdTableTable make_fwd_table_table() {
+    return {{{fwd_table_types<T, CDF97, NONSEP>(), fwd_table_types<T, CDF97, SEP>()},
+             {fwd_table_types<T, CDF53, NONSEP>(), fwd_table_types<T, CDF53, SEP>()}}};
+}
+template <typename T>
+constexpr InvTableTable make_inv_table_table() {
+    return {{{inv_table_types<T, CDF97, NONSEP>(), inv_table_types<T, CDF97, SEP>()},
+             {inv_table_types<T, CDF53, NONSEP>(), inv_table_types<T, CDF53, SEP>()}}};
 }
 
 template <int WV, int SCH, typename TIN, typename TLL, typename TB, int... I>
@@ -249,6 +302,8 @@ extern FwdTable kFwdF32, kFwdF16, kFwdBF16;
 extern InvTable kInvF32, kInvF16, kInvBF16;
 extern FwdBatchTable kFwdBatchF32, kFwdBatchF16, kFwdBatchBF16;
 extern InvBatchTable kInvBatchF32, kInvBatchF16, kInvBatchBF16;
+extern FwdTableTable kFwdPlanF32, kFwdPlanF16, kFwdPlanBF16;
+extern InvTableTable kInvPlanF32, kInvPlanF16, kInvPlanBF16;
 extern FwdTailTable kFwdTailF32, kFwdTailF16, kFwdTailBF16;
 extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
 extern FwdLdsTable kFwdLds;

@@ -1,0 +1,7 @@
+// Kernel instantiations: planned-batch (device table) inv launches with f32
+// storage of user-visible buffers.
+#include "dwt2_table.hpp"
+
+namespace dwt2 {
+InvTableTable kInvPlanF32 = make_inv_table_table<float>();
+}  // namespace dwt2

@@ -1,8 +1,9 @@
-"""Batched launches of uneven images, and their HIP-graph capture.
+"""Planned batches of uneven images, and their HIP-graph capture.
 
 A batch runs the same per-quad arithmetic as the single-image path with the
 same tile configuration, so results must agree bit for bit; against the
-oracle the FP32 bound is 1e-5 of max|x|.
+oracle the FP32 bound is 1e-5 of max|x|. With one tile configuration for
+every size class, each level is one launch over all images.
 """
 import numpy as np
 import pytest
@@ -53,14 +54,56 @@ def test_batch_inverse_round_trip_and_mixed_classes():
         assert torch.equal(dwt.inverse(c, "cdf97", 3), r)
 
 
-def test_batch_more_than_one_chunk_per_class():
+def test_batch_of_many_images_is_one_launch_per_level():
     imgs = [torch.from_numpy(synthetic.uniform_image(64, 96, seed=i)).to("cuda")
-            for i in range(80)]                         # 80 > 36 images in one class
+            for i in range(80)]
     plan = dwb.BatchPlan.forward(imgs, 2)
+    assert plan.launches() == (2, [1, 1])
     plan.run()
     torch.cuda.synchronize()
     for x, c in zip(imgs, plan.outputs):
         assert torch.equal(dwt.forward(x, "cdf97", 2), c)
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_256_uneven_images_one_launch_per_level_persistent_or_not(inverse):
+    """The batch workload's shape (256 images, sides log-uniform, multiples of
+    32, three levels) at sides up to 512: one launch per level whatever the
+    size classes, and the persistent grid gives the same bits."""
+    imgs = _images(256, lo=64, hi=512, seed=3)
+    src = imgs
+    if inverse:
+        fwd = dwb.BatchPlan.forward(imgs, 3)
+        fwd.run()
+        src = fwd.outputs
+    mk = dwb.BatchPlan.inverse_of if inverse else dwb.BatchPlan.forward
+    a = mk(src, 3)
+    b = mk(src, 3, persistent=True)
+    assert a.launches() == (3, [1, 1, 1])
+    a.run()
+    b.run()
+    torch.cuda.synchronize()
+    for k, (x, p, q) in enumerate(zip(src, a.outputs, b.outputs)):
+        assert torch.equal(p, q), k
+        single = dwt.inverse(x, "cdf97", 3) if inverse else dwt.forward(x, "cdf97", 3)
+        assert torch.equal(single, p), k
+
+
+def test_class_tiles_differing_per_class_give_identical_outputs():
+    """Per-class tuned tiles split a level into one launch per configuration
+    in use; the results equal the default tiles' bit for bit."""
+    imgs = _images(24, lo=64, hi=1024, seed=6)
+    classes = sorted({dwb.size_class(x.shape[1], x.shape[0]) for x in imgs})
+    assert len(classes) >= 2
+    ref = dwb.BatchPlan.forward(imgs, 2)
+    mixed = dwb.BatchPlan.forward(imgs, 2, class_tiles=[0, 2, 1, 3])
+    total, per = mixed.launches()
+    assert per[0] == len(classes) and total >= 3
+    ref.run()
+    mixed.run()
+    torch.cuda.synchronize()
+    for a, b in zip(ref.outputs, mixed.outputs):
+        assert torch.equal(a, b)
 
 
 def test_batch_every_2d_tile_config_identical():
@@ -108,8 +151,7 @@ def test_batch_16_bit_equals_single(dtype):
 def test_batch_rejects_invalid_image_before_launch():
     imgs = _images(3, seed=1)
     bad = torch.zeros(48, 64, device="cuda")            # 48 not divisible by 2^5
-    plan = dwb.BatchPlan.forward(imgs + [bad], 5)
     with pytest.raises(dwt.DWT2Error):
-        plan.run()
+        dwb.BatchPlan.forward(imgs + [bad], 5)
     with pytest.raises(dwt.DWT2Error):
-        dwb.run_batch(imgs, imgs, [None] * 3, levels=1)  # dst overlaps src
+        dwb.make_plan(imgs, imgs, [None] * 3, levels=1)  # dst overlaps src
