@@ -80,23 +80,44 @@ def level_bytes(W, H, levels, es_store):
     return out
 
 
-def executed_bytes(W, H, levels, es_store, fused):
-    """Algorithmic bytes per direction of the launches actually made: the
-    per-level launches as in level_bytes, and for the last `fused` levels one
-    read of the first fused level's input plus one write of every fused
-    level's detail bands and the final LL (their intermediate LL stays on
-    chip)."""
-    lb = level_bytes(W, H, levels, es_store)
-    if fused < 2:
-        return sum(lb)
-    k = levels - fused + 1
+def launch_units(levels, fused, head):
+    """The launches of one direction of the chain, finest first: (kind, first
+    level, number of levels) with kind "head" (levels 1 and 2 fused), "level"
+    (one level) or "tail" (the last `fused` levels fused)."""
+    units = []
+    j = 1
+    if head:
+        units.append(("head", 1, 2))
+        j = 3
+    k = levels - fused + 1 if fused >= 2 else levels + 1
+    while j < k:
+        units.append(("level", j, 1))
+        j += 1
+    if fused >= 2:
+        units.append(("tail", k, fused))
+    return units
+
+
+def unit_bytes(W, H, levels, es_store, unit):
+    """Algorithmic bytes of one forward launch (the inverse is symmetric): one
+    read of its first level's input, one write of every level's detail bands
+    and of its last level's LL. Low-low bands between its levels stay on chip;
+    the image and bands use the storage size, intermediate LL is FP32."""
+    _, k, n = unit
     w, h = W >> (k - 1), H >> (k - 1)
-    tail = w * h * (es_store if k == 1 else 4)
-    for j in range(k, levels + 1):
+    b = w * h * (es_store if k == 1 else 4)
+    for j in range(k, k + n):
         px = (W >> (j - 1)) * (H >> (j - 1))
-        tail += (px // 4) * 3 * es_store
-    tail += (W >> levels) * (H >> levels) * es_store
-    return sum(lb[:k - 1]) + tail
+        b += (px // 4) * 3 * es_store
+    last = k + n - 1
+    b += (W >> last) * (H >> last) * (es_store if last == levels else 4)
+    return b
+
+
+def executed_bytes(W, H, levels, es_store, fused, head=False):
+    """Algorithmic bytes per direction of the launches actually made."""
+    return sum(unit_bytes(W, H, levels, es_store, u)
+               for u in launch_units(levels, fused, head))
 
 
 def make_image(W, H, kind, seed):
@@ -219,14 +240,16 @@ def run_gpu(args, x_np, scheme):
             torch.cuda.synchronize()
             concurrent_ms = c0.elapsed_time(c1)
 
-    # per-level kernel durations: each level's launch repeated back to back,
-    # bracketed by events on the launch stream, buffers rotating
+    # per-launch kernel durations: each launch of the chain repeated back to
+    # back, bracketed by events on the launch stream, buffers rotating
     R = 40
     fwd_ms, inv_ms = [], []
     # the exchange-ablation schemes never fuse levels
-    fused = dwt.fused_levels(W, H, L) if args.fuse == "auto" and not scheme.endswith("_lds") else 0
-    k_tail = L + 1 - fused if fused else L + 1
-    for j in range(1, k_tail + 1 if fused else L + 1):
+    lds = scheme.endswith("_lds")
+    fused = dwt.fused_levels(W, H, L) if args.fuse == "auto" and not lds else 0
+    head = args.fuse == "auto" and not lds and dwt.head_levels(W, H, L) == 2
+    units = launch_units(L, fused, head)
+    for kind, j, nlev in units:
         w, h = W >> (j - 1), H >> (j - 1)
         for direction in ("forward", "inverse"):
             def once(k):
@@ -245,16 +268,26 @@ def run_gpu(args, x_np, scheme):
                     img = src if direction == "forward" else rec
                 else:
                     img = ws[:w * h].view(h, w)
-                if j == k_tail:
-                    # the fused launch of levels k..L on the chain's buffers:
-                    # the level-k input in the workspace, the bands in coef
+                if kind == "head":
+                    # levels 1 and 2 of the full image: the bands go to their
+                    # places in coef; the level-2 LL to coef's corner instead
+                    # of the workspace (the same FP32 kernel)
+                    if direction == "forward":
+                        dwt.forward(src, args.wavelet, 2, scheme, out=coef, workspace=ws,
+                                    tiles=[_lib.TILE_HEAD] * 2)
+                    else:
+                        dwt.inverse(coef, args.wavelet, 2, scheme, out=rec, workspace=ws,
+                                    tiles=[_lib.TILE_HEAD] * 2)
+                elif kind == "tail":
+                    # the fused launch of levels j..L on the chain's buffers:
+                    # the level-j input in the workspace, the bands in coef
                     sub = coef[:h, :w]
                     if direction == "forward":
-                        dwt.forward(img, args.wavelet, fused, scheme, out=sub, workspace=tws,
-                                    tiles=[_lib.TILE_TAIL] * fused)
+                        dwt.forward(img, args.wavelet, nlev, scheme, out=sub, workspace=tws,
+                                    tiles=[_lib.TILE_TAIL] * nlev)
                     else:
-                        dwt.inverse(sub, args.wavelet, fused, scheme, out=img, workspace=tws,
-                                    tiles=[_lib.TILE_TAIL] * fused)
+                        dwt.inverse(sub, args.wavelet, nlev, scheme, out=img, workspace=tws,
+                                    tiles=[_lib.TILE_TAIL] * nlev)
                 elif direction == "forward":
                     dwt.forward_level(img, ll, hl, lh, hh, args.wavelet, scheme)
                 elif j == 1:
@@ -264,13 +297,14 @@ def run_gpu(args, x_np, scheme):
                     dwt.inverse(coef, args.wavelet, 1, scheme, out=rec, workspace=ws)
                 else:
                     dwt.inverse_level(ll, hl, lh, hh, img, args.wavelet, scheme)
-            if j == k_tail:
-                if args.dtype != "f32" and k_tail > 1:
-                    # the fused kernel of a 16-bit chain reads FP32 and writes
-                    # 16-bit bands; a same-type call cannot reproduce it
-                    (fwd_ms if direction == "forward" else inv_ms).append(None)
-                    continue
-                tws = dwt.make_workspace(w, h, fused, dev)
+            if kind != "level" and args.dtype != "f32" and (kind == "head" or j > 1):
+                # a 16-bit chain's fused launches keep an FP32 LL on one side
+                # (the head's level-2 output, the tail's input); a standalone
+                # call of the same storage type is a different kernel
+                (fwd_ms if direction == "forward" else inv_ms).append(None)
+                continue
+            if kind == "tail":
+                tws = dwt.make_workspace(w, h, nlev, dev)
             for k in range(5):
                 once(k)
             # R launches captured in one graph, so host launch overhead does
@@ -292,7 +326,8 @@ def run_gpu(args, x_np, scheme):
 
     out = dict(total_ms=total_ms, wall_s=wall, fwd_level_ms=fwd_ms, inv_level_ms=inv_ms,
                concurrent_ms=concurrent_ms, step_ms=step_ms, warm_ms=warm_ms,
-               fused_levels=list(range(k_tail, L + 1)) if fused else [],
+               units=units, fused_levels=list(range(L - fused + 1, L + 1)) if fused else [],
+               head=head,
                coef=eager_coef.float().cpu().numpy(), rec=eager_rec.float().cpu().numpy(),
                stored=sets[0][0].float().cpu().numpy(), graph=bool(graphs),
                replay_matches_eager=replay_matches)
@@ -631,23 +666,25 @@ def main():
     gpx = W * H / (ms_step * 1e-3) / 1e9
     alg_bytes_step = 2 * sum(lb)
 
+    # the dominant kernel is the chain's first launch: the fused levels 1-2
+    # (head), the level-1 launch, or the fused launch of every level (small
+    # images); its bytes are that launch's algorithmic bytes
     f1, i1 = main_run["fwd_level_ms"][0], main_run["inv_level_ms"][0]
     dom = "inverse" if i1 > f1 else "forward"
     dom_ms = max(f1, i1)
-    # the dominant kernel is the level-1 launch, or the fused launch when
-    # every level is fused (small images): its bytes are all levels' bytes
-    all_fused = 1 in main_run["fused_levels"]
-    dom_bytes = sum(lb) if all_fused else lb[0]
+    unit0 = main_run["units"][0]
+    dom_bytes = unit_bytes(W, H, L, es, unit0)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     import paper_1705_08266_amd as dwt
     _, qpl, rows, waves, _, _ = dwt.tile_configs(args.wavelet)[dwt.default_tile(W, H)]
-    kernel_key = (f"{dom}_level1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
-                  f"_q{qpl}r{rows}w{waves}")
+    unit_name = {"head": "fused levels 1-2", "level": "level 1",
+                 "tail": f"fused levels 1-{L}"}[unit0[0]]
+    kernel_key = (f"{dom}_{unit0[0]}1_{args.wavelet}_{args.scheme}_{args.dtype}_{W}x{H}"
+                  + (f"_q{qpl}r{rows}w{waves}" if unit0[0] == "level" else ""))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if all_fused else load_traffic(kernel_key),
-                    kernel=(f"{dom} fused levels 1-{L}" if all_fused else f"{dom} level 1")
-                    + f" ({args.scheme})",
+                    traffic=load_traffic(kernel_key),
+                    kernel=f"{dom} {unit_name} ({args.scheme})",
                     bytes_per_launch=dom_bytes, avg_launch_ms=round(dom_ms, 5),
                     copy_gbs=round(copy_gbs, 1), copy_kind=f"{copy_kind}, 1 GiB",
                     frac_of_copy=round(achieved / copy_gbs, 4))
@@ -668,10 +705,14 @@ def main():
         roofline=roofline,
         hbm_frac_whole_step=round(alg_bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         algorithmic_bytes_per_step=alg_bytes_step,
-        executed_bytes_per_step=2 * executed_bytes(W, H, L, es, len(main_run["fused_levels"])),
-        level_ms=dict(forward=rounded(main_run["fwd_level_ms"]),
-                      inverse=rounded(main_run["inv_level_ms"])),
-        fused_levels=main_run["fused_levels"],
+        executed_bytes_per_step=2 * executed_bytes(W, H, L, es, len(main_run["fused_levels"]),
+                                                   main_run["head"]),
+        launch_ms=dict(launches=[f"{k} {j}" + (f"-{j + n - 1}" if n > 1 else "")
+                                 for k, j, n in main_run["units"]],
+                       forward=rounded(main_run["fwd_level_ms"]),
+                       inverse=rounded(main_run["inv_level_ms"])),
+        fused_levels=dict(head=[1, 2] if main_run["head"] else [],
+                          tail=main_run["fused_levels"]),
         launch=("one captured HIP graph per buffer set (forward + inverse chain)"
                 if main_run["graph"] else "eager launches"),
         two_streams=(None if main_run["concurrent_ms"] is None else dict(
@@ -696,9 +737,10 @@ def main():
         s1 = max(sep_run["fwd_level_ms"][0], sep_run["inv_level_ms"][0])
         result["separable"] = dict(
             value=round(W * H / (s_ms * 1e-3) / 1e9, 3), ms_per_step=round(s_ms, 5),
-            level1_gbs=round(lb[0] / (s1 * 1e-3) / 1e9, 1),
-            level_ms=dict(forward=rounded(sep_run["fwd_level_ms"]),
-                          inverse=rounded(sep_run["inv_level_ms"])))
+            first_launch_gbs=round(unit_bytes(W, H, L, es, sep_run["units"][0])
+                                   / (s1 * 1e-3) / 1e9, 1),
+            launch_ms=dict(forward=rounded(sep_run["fwd_level_ms"]),
+                           inverse=rounded(sep_run["inv_level_ms"])))
 
     if ablation:
         result["exchange_ablation"] = {

@@ -166,6 +166,8 @@ int dwt2_forward_no_alloc(const void *src, const dwt2_desc *src_d, void *coef,
 
 /* Tile id that marks a level as part of the fused tail launch. */
 #define DWT2_TILE_TAIL (-2)
+/* Tile id that marks levels 1 and 2 as one fused launch (the "head"). */
+#define DWT2_TILE_HEAD (-3)
 #define DWT2_TAIL_MAX 3
 #define DWT2_TAIL_AUTO_PIXELS (1 << 20)
 
@@ -175,6 +177,14 @@ int dwt2_forward_no_alloc(const void *src, const dwt2_desc *src_d, void *coef,
  * rejects. */
 int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels);
 
+/* Number of leading levels (0 or 2) that dwt2_forward and dwt2_inverse run
+ * as one launch: levels 1 and 2 are fused, their low-low band kept on chip,
+ * whenever there are two or more levels and the fused tail starts at level 3
+ * or later (Sec. 5 names fusing several consecutive steps as a way to cut
+ * memory traffic). Returns DWT2_ERR_INVALID_ARG for sizes the transform
+ * rejects. */
+int dwt2_head_levels(int32_t width, int32_t height, int32_t levels);
+
 /* dwt2_forward (dwt2_inverse) with two tuning and timing hooks; results are
  * identical to the plain calls.
  *   tiles : NULL to let the library choose, else `levels` tile ids
@@ -182,12 +192,15 @@ int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels);
  *           DWT2_TILE_TAIL for each of the last 2..DWT2_TAIL_MAX levels:
  *           those run fused in one launch (one workgroup computes every
  *           fused level for its block; intermediate low-low bands stay in
- *           LDS). Entry j belongs to level j+1.
+ *           LDS), or DWT2_TILE_HEAD for both levels 1 and 2 (fused the same
+ *           way; the tail must then start at level 3 or later). Entry j
+ *           belongs to level j+1.
  *   level_events : NULL, or 2*levels events; events [2j] and [2j+1] are
  *           recorded on `stream` before and after the launch of level j+1.
- *           For fused levels the first fused level's pair brackets the fused
- *           launch and the other fused levels' pairs are both recorded after
- *           it. */
+ *           For fused tail levels the first fused level's pair brackets the
+ *           fused launch and the other fused levels' pairs are both recorded
+ *           after it; a fused head is bracketed by level 1's pair, and level
+ *           2's pair is recorded after it. */
 int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const dwt2_desc *coef_d,
                     dwt2_wavelet wavelet, int32_t levels, dwt2_boundary boundary,
                     dwt2_scheme scheme, void *workspace, size_t workspace_bytes,

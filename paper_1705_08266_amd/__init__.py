@@ -212,5 +212,12 @@ def fused_levels(width: int, height: int, levels: int) -> int:
     return n
 
 
+def head_levels(width: int, height: int, levels: int) -> int:
+    """Leading levels (0 or 2) the library runs as one fused launch by default."""
+    n = int(load().dwt2_head_levels(width, height, levels))
+    _lib.check(min(n, 0), "dwt2_head_levels")
+    return n
+
+
 def default_tile(width, height, wavelet="cdf97", scheme="nonseparable", dtype=_lib.F32):
     return int(load().dwt2_default_tile(width, height, _wavelet(wavelet), _scheme(scheme), dtype))

@@ -17,6 +17,7 @@ EXT_WHOLE_SAMPLE_SYMMETRIC = 0
 F32, F16, BF16 = 0, 1, 2
 NONSEPARABLE, SEPARABLE, NONSEPARABLE_LDS, SEPARABLE_LDS = 0, 1, 2, 3
 TILE_TAIL = -2            # tiles[j] of a level that runs in the fused tail launch
+TILE_HEAD = -3            # tiles[0] and tiles[1]: levels 1 and 2 in one fused launch
 TAIL_MAX = 3
 TAIL_AUTO_PIXELS = 1 << 20
 STATIC_WORKSPACE_BYTES = 64 << 20   # DWT2_STATIC_WORKSPACE_BYTES
@@ -92,6 +93,7 @@ SIGNATURES = {
     "dwt2_forward_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_inverse_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_fused_levels": (ctypes.c_int, [_i32, _i32, _i32]),
+    "dwt2_head_levels": (ctypes.c_int, [_i32, _i32, _i32]),
     "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dwt2_last_hip_error": (ctypes.c_int, []),
     "dwt2_version": (ctypes.c_int, []),

@@ -190,13 +190,20 @@ const InvTailTable &inv_tail_table(int dt) {
     return dt == DWT2_F32 ? kInvTailF32 : dt == DWT2_F16 ? kInvTailF16 : kInvTailBF16;
 }
 
+const FwdHeadTable &fwd_head_table(int dt) {
+    return dt == DWT2_F32 ? kFwdHeadF32 : dt == DWT2_F16 ? kFwdHeadF16 : kFwdHeadBF16;
+}
+const InvHeadTable &inv_head_table(int dt) {
+    return dt == DWT2_F32 ? kInvHeadF32 : dt == DWT2_F16 ? kInvHeadF16 : kInvHeadBF16;
+}
+
 static_assert(DWT2_TAIL_MAX == kTailMax, "header and kernels agree on the fused depth");
 
 // First fused level (1-based) of an L-level transform, or levels + 1 when no
 // level is fused. With explicit tiles the DWT2_TILE_TAIL entries must form a
 // suffix of 2..kTailMax levels (else -1).
 int tail_start(int W, int H, int levels, const int32_t *tiles) {
-    if (tiles) {
+    if (tiles) {   // (head entries are validated separately)
         int k = levels + 1;
         while (k > 1 && tiles[k - 2] == DWT2_TILE_TAIL) --k;
         for (int j = 1; j < k; ++j)
@@ -210,6 +217,16 @@ int tail_start(int W, int H, int levels, const int32_t *tiles) {
            (int64_t)(W >> (k - 2)) * (int64_t)(H >> (k - 2)) <= DWT2_TAIL_AUTO_PIXELS)
         --k;
     return levels + 1 - k >= 2 ? k : levels + 1;
+}
+
+// True when levels 1 and 2 run as one fused launch (dwt2_head.hpp): when
+// asked for with DWT2_TILE_HEAD in tiles[0] and tiles[1], or by default when
+// there are two or more levels and the fused tail starts at level 3 or later
+// (k: first tail level). The exchange-ablation schemes never fuse.
+bool use_head(int levels, const int32_t *tiles, int k, int scheme) {
+    if (lds_scheme(scheme) || levels < 2) return false;
+    if (tiles) return tiles[0] == DWT2_TILE_HEAD;
+    return k >= 3;
 }
 
 // Block side and region extensions of a fused tail (see dwt2_tail.hpp).
@@ -398,14 +415,23 @@ int check_multi(const void *x, const dwt2_desc *xd, const void *y, const dwt2_de
     if ((W % (1 << levels)) != 0 || (H % (1 << levels)) != 0) return DWT2_ERR_INVALID_ARG;
     if (xd->pitch < W || yd->pitch < W) return DWT2_ERR_INVALID_ARG;
     if (tiles) {
-        for (int j = 0; j < levels; ++j)
+        for (int j = 0; j < levels; ++j) {
+            if (tiles[j] == DWT2_TILE_HEAD) {   // levels 1 and 2 only, both marked
+                if (j > 1 || levels < 2 || tiles[0] != DWT2_TILE_HEAD ||
+                    tiles[1] != DWT2_TILE_HEAD)
+                    return DWT2_ERR_UNSUPPORTED;
+                continue;
+            }
             if (tiles[j] < DWT2_TILE_TAIL || tiles[j] >= kNumTiles) return DWT2_ERR_UNSUPPORTED;
-        if (tail_start(W, H, levels, tiles) < 0) return DWT2_ERR_UNSUPPORTED;
+        }
+        const int k = tail_start(W, H, levels, tiles);
+        if (k < 0 || (tiles[0] == DWT2_TILE_HEAD && k < 3)) return DWT2_ERR_UNSUPPORTED;
     }
     if (lds_scheme(scheme)) {   // no fused tail; FP32 2-D tiles only
         if (xd->dtype != DWT2_F32) return DWT2_ERR_UNSUPPORTED;
         for (int j = 0; tiles && j < levels; ++j)
-            if (tiles[j] == DWT2_TILE_TAIL) return DWT2_ERR_UNSUPPORTED;
+            if (tiles[j] == DWT2_TILE_TAIL || tiles[j] == DWT2_TILE_HEAD)
+                return DWT2_ERR_UNSUPPORTED;
     }
     const Region sx = region_of(x, H, W, xd->pitch, xd->dtype);
     const Region sy = region_of(y, H, W, yd->pitch, yd->dtype);
@@ -718,6 +744,13 @@ int dwt2_fused_levels(int32_t width, int32_t height, int32_t levels) {
     return levels + 1 - tail_start(width, height, levels, nullptr);
 }
 
+int dwt2_head_levels(int32_t width, int32_t height, int32_t levels) {
+    if (levels < 1 || levels > 16 || width < 2 || height < 2 ||
+        (width % (1 << levels)) != 0 || (height % (1 << levels)) != 0)
+        return DWT2_ERR_INVALID_ARG;
+    return use_head(levels, nullptr, tail_start(width, height, levels, nullptr), 0) ? 2 : 0;
+}
+
 int dwt2_tile_config_count(void) { return kNumTiles; }
 
 int dwt2_tile_config_info(int32_t tile, dwt2_wavelet wavelet, int32_t *quads_per_lane, int32_t *rows,
@@ -787,7 +820,9 @@ int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const d
     char *cbase = static_cast<char *>(coef);
     const int64_t cp = coef_d->pitch;
     const int k = lds_scheme(scheme) ? levels + 1 : tail_start(W, H, levels, tiles);
+    const bool head = use_head(levels, tiles, k, scheme);
     FwdTail tail;
+    FwdHead hd;
     for (int j = 1; j <= levels; ++j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
         const void *in = j == 1 ? src : (const void *)ws[(j - 2) & 1];
@@ -803,6 +838,21 @@ int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const d
             tail.lv[j - k] = fwd_params(in, in_pitch, in_dt, w, h, ll, ll_pitch, ll_dt, hl, lh,
                                         hh, cp, T, wavelet, 0);
             tail.lv[j - k].vec_in = aligned(in, in_pitch, in_dt, 2);
+            continue;
+        }
+        if (head && j <= 2) {   // levels 1 and 2: one launch once both are planned
+            (j == 1 ? hd.l1 : hd.l2) = fwd_params(in, in_pitch, in_dt, w, h, ll, ll_pitch, ll_dt,
+                                                  hl, lh, hh, cp, T, wavelet, 0);
+            if (j == 1) continue;
+            hd.tiles_x = (hd.l2.nqx + FwdHeadGeom::FOX2 - 1) / FwdHeadGeom::FOX2;
+            hd.tiles_y = (hd.l2.nqy + FwdHeadGeom::FOY2 - 1) / FwdHeadGeom::FOY2;
+            if ((st = record(level_events, 0, s))) return st;
+            const hipError_t e =
+                fwd_head_table(T)[wavelet][scheme][T == DWT2_F32][levels > 2 || T == DWT2_F32](
+                    hd, s);
+            if (e != hipSuccess) return hip_fail(e);
+            for (int ev = 1; ev <= 3; ++ev)
+                if ((st = record(level_events, ev, s))) return st;
             continue;
         }
         const int tile = tiles ? tiles[j - 1] : -1;
@@ -858,7 +908,9 @@ int dwt2_inverse_ex(const void *coef, const dwt2_desc *coef_d, void *dst, const 
     const char *cbase = static_cast<const char *>(coef);
     const int64_t cp = coef_d->pitch;
     const int k = lds_scheme(scheme) ? levels + 1 : tail_start(W, H, levels, tiles);
+    const bool head = use_head(levels, tiles, k, scheme);
     InvTail tail;
+    InvHead hd;
     for (int j = levels; j >= 1; --j) {
         const int w = W >> (j - 1), h = H >> (j - 1);
         const void *ll = j == levels ? coef : (const void *)ws[(j - 1) & 1];
@@ -897,12 +949,28 @@ int dwt2_inverse_ex(const void *coef, const dwt2_desc *coef_d, void *dst, const 
             }
             continue;
         }
-        const int tile = tiles ? tiles[j - 1] : -1;
-        if ((st = record(level_events, 2 * (j - 1), s))) return st;
         // the reconstructed image is the transform's last write
         const int64_t image_bytes = (int64_t)W * H * (int64_t)es;
         const bool stream_out = j == 1 && image_bytes >= kStreamOutMinBytes &&
                                 image_bytes <= kStreamOutMaxBytes;
+        if (head && j <= 2) {   // levels 2 and 1: one launch once both are planned
+            (j == 2 ? hd.l2 : hd.l1) = inv_params(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out,
+                                                  out_pitch, out_dt, w, h, wavelet, 0);
+            if (j == 2) continue;
+            hd.l1.stream_out = stream_out;
+            hd.tiles_x = (hd.l1.nqx + FwdHeadGeom::IOX1 - 1) / FwdHeadGeom::IOX1;
+            hd.tiles_y = (hd.l1.nqy + FwdHeadGeom::IOY1 - 1) / FwdHeadGeom::IOY1;
+            if ((st = record(level_events, 0, s))) return st;
+            const hipError_t e =
+                inv_head_table(T)[wavelet][scheme][levels > 2 || T == DWT2_F32][T == DWT2_F32](
+                    hd, s);
+            if (e != hipSuccess) return hip_fail(e);
+            for (int ev = 1; ev <= 3; ++ev)
+                if ((st = record(level_events, ev, s))) return st;
+            continue;
+        }
+        const int tile = tiles ? tiles[j - 1] : -1;
+        if ((st = record(level_events, 2 * (j - 1), s))) return st;
         st = inv_level(ll, ll_pitch, ll_dt, hl, lh, hh, cp, T, out, out_pitch, out_dt, w, h,
                        wavelet, scheme, tile, s, stream_out);
         if (st) return st;

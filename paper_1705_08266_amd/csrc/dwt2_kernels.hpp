@@ -287,7 +287,8 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_level_kernel(FwdParams prm) {
 // Outside the level, each polyphase component is extended through the
 // symmetric extension of the pixel grid it lives on: quad (i, j) component b
 // stands for pixel (2i+1, 2j), and so on.
-template <int QPL, int ROWS, typename TLL, typename TB>
+// WITH_LL false: the detail bands only (q.a is left as it is).
+template <int QPL, int ROWS, typename TLL, typename TB, bool WITH_LL = true>
 __device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams &prm, int qx0,
                                             int qy0) {
     const TLL *ll = static_cast<const TLL *>(prm.ll);
@@ -309,7 +310,7 @@ __device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams
             const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
 #pragma unroll
             for (int i = 0; i < QPL; ++i) {
-                q.a[r][i] = to_float(ll[(int64_t)ye * prm.ll_pitch + xe[i]]);
+                if constexpr (WITH_LL) q.a[r][i] = to_float(ll[(int64_t)ye * prm.ll_pitch + xe[i]]);
                 q.b[r][i] = to_float(hl[(int64_t)ye * prm.band_pitch + xo[i]]);
                 q.c[r][i] = to_float(lh[(int64_t)yo * prm.band_pitch + xe[i]]);
                 q.d[r][i] = to_float(hh[(int64_t)yo * prm.band_pitch + xo[i]]);
@@ -329,17 +330,17 @@ __device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams
         const int gy = qy0 + r;
         const int64_t ye = mirror(2 * gy, prm.h) >> 1;
         const int64_t yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
-        rl[r] = make_rsrc(ll + ye * prm.ll_pitch, lb);
+        if constexpr (WITH_LL) rl[r] = make_rsrc(ll + ye * prm.ll_pitch, lb);
         rh[r] = make_rsrc(hl + ye * prm.band_pitch, bb);
         rv[r] = make_rsrc(lh + yo * prm.band_pitch, bb);
         rd[r] = make_rsrc(hh + yo * prm.band_pitch, bb);
-        load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
+        if constexpr (WITH_LL) load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
         load_vec<TB, QPL>(rh[r], co.off_a, q.b[r]);
         load_vec<TB, QPL>(rv[r], ce.off_a, q.c[r]);
         load_vec<TB, QPL>(rd[r], co.off_a, q.d[r]);
     }
     if (!wave_all(plain)) {
-        fix_cols<TLL>(rl, cl, q.a);
+        if constexpr (WITH_LL) fix_cols<TLL>(rl, cl, q.a);
         fix_cols<TB>(rh, co, q.b);
         fix_cols<TB>(rv, ce, q.c);
         fix_cols<TB>(rd, co, q.d);

@@ -5,6 +5,7 @@
 #include <utility>
 
 #include "dwt2_kernels.hpp"
+#include "dwt2_head.hpp"
 #include "dwt2_tail.hpp"
 
 namespace dwt2 {
@@ -266,6 +267,53 @@ constexpr InvTailTable make_inv_tail_table() {
              {inv_tail_depths<T, CDF53, NONSEP>(), inv_tail_depths<T, CDF53, SEP>()}}};
 }
 
+// Fused finest levels (head). Forward index [wavelet][scheme][level j's input
+// is FP32][level j+1's low-low output is FP32]; inverse [wavelet][scheme]
+// [level j+1's low-low input is FP32][level j's output is FP32]. The detail
+// bands are in the storage type; the band between the two levels is FP32 in
+// LDS. One configuration: 12 wavefronts of 4 quad rows.
+constexpr int kHeadRows = 4, kHeadWaves = 12;
+using FwdHeadGeom = HeadGeom<kHeadRows, kHeadWaves>;
+using FwdHeadLauncher = hipError_t (*)(const FwdHead &, hipStream_t);
+using InvHeadLauncher = hipError_t (*)(const InvHead &, hipStream_t);
+
+template <int WV, int SCH, typename TIN, typename TLL, typename T>
+hipError_t launch_fwd_head(const FwdHead &h, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_head_kernel<WV, SCH, kHeadRows, kHeadWaves, TIN, TLL, T>),
+                       dim3(h.tiles_x * h.tiles_y), dim3(64 * kHeadWaves), 0, s, h);
+    return hipGetLastError();
+}
+template <int WV, int SCH, typename TLL, typename T, typename TOUT>
+hipError_t launch_inv_head(const InvHead &h, hipStream_t s) {
+    hipLaunchKernelGGL((inv_head_kernel<WV, SCH, kHeadRows, kHeadWaves, TLL, T, TOUT>),
+                       dim3(h.tiles_x * h.tiles_y), dim3(64 * kHeadWaves), 0, s, h);
+    return hipGetLastError();
+}
+
+using FwdHeadTable = std::array<std::array<std::array<std::array<FwdHeadLauncher, 2>, 2>, 2>, 2>;
+using InvHeadTable = std::array<std::array<std::array<std::array<InvHeadLauncher, 2>, 2>, 2>, 2>;
+
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<FwdHeadLauncher, 2>, 2> fwd_head_types() {
+    return {{{&launch_fwd_head<WV, SCH, T, T, T>, &launch_fwd_head<WV, SCH, T, float, T>},
+             {&launch_fwd_head<WV, SCH, float, T, T>, &launch_fwd_head<WV, SCH, float, float, T>}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<InvHeadLauncher, 2>, 2> inv_head_types() {
+    return {{{&launch_inv_head<WV, SCH, T, T, T>, &launch_inv_head<WV, SCH, T, T, float>},
+             {&launch_inv_head<WV, SCH, float, T, T>, &launch_inv_head<WV, SCH, float, T, float>}}};
+}
+template <typename T>
+constexpr FwdHeadTable make_fwd_head_table() {
+    return {{{fwd_head_types<T, CDF97, NONSEP>(), fwd_head_types<T, CDF97, SEP>()},
+             {fwd_head_types<T, CDF53, NONSEP>(), fwd_head_types<T, CDF53, SEP>()}}};
+}
+template <typename T>
+constexpr InvHeadTable make_inv_head_table() {
+    return {{{inv_head_types<T, CDF97, NONSEP>(), inv_head_types<T, CDF97, SEP>()},
+             {inv_head_types<T, CDF53, NONSEP>(), inv_head_types<T, CDF53, SEP>()}}};
+}
+
 // The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels only, index [wavelet][scheme - NONSEP_LDS][config].
 using FwdLdsTable = std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>;
 using InvLdsTable = std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>;
@@ -305,6 +353,8 @@ extern InvBatchTable kInvBatchF32, kInvBatchF16, kInvBatchBF16;
 extern FwdTableTable kFwdPlanF32, kFwdPlanF16, kFwdPlanBF16;
 extern InvTableTable kInvPlanF32, kInvPlanF16, kInvPlanBF16;
 extern FwdTailTable kFwdTailF32, kFwdTailF16, kFwdTailBF16;
+extern FwdHeadTable kFwdHeadF32, kFwdHeadF16, kFwdHeadBF16;
+extern InvHeadTable kInvHeadF32, kInvHeadF16, kInvHeadBF16;
 extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
 extern FwdLdsTable kFwdLds;
 extern InvLdsTable kInvLds;

@@ -1,0 +1,7 @@
+// Kernel instantiations: fused finest levels (head), inv, f32 storage of
+// user-visible buffers.
+#include "dwt2_table.hpp"
+
+namespace dwt2 {
+InvHeadTable kInvHeadF32 = make_inv_head_table<float>();
+}  // namespace dwt2

@@ -256,3 +256,27 @@ def test_no_alloc_checks_before_touching_the_device():
     assert _lib.STATIC_WORKSPACE_BYTES == 64 << 20
     header = open(HEADER).read()
     assert "#define DWT2_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)" in header
+
+
+def test_head_tile_ids():
+    """DWT2_TILE_HEAD marks exactly levels 1 and 2, with the tail (if any)
+    starting at level 3 or later."""
+    U, W, HD, T = _lib.ERR_UNSUPPORTED, _lib.ERR_WORKSPACE, _lib.TILE_HEAD, _lib.TILE_TAIL
+
+    def tiles(*ids):
+        return (ctypes.c_int32 * len(ids))(*ids)
+
+    assert _fwd(levels=3, tiles=tiles(HD, HD, 0)) == W          # accepted up to the workspace
+    assert _fwd(levels=5, tiles=tiles(HD, HD, T, T, T)) == W
+    assert _fwd(levels=3, tiles=tiles(HD, 0, 0)) == U           # level 2 not marked
+    assert _fwd(levels=3, tiles=tiles(0, HD, HD)) == U          # not levels 1 and 2
+    assert _fwd(levels=1, tiles=tiles(HD)) == U                 # one level
+    assert _fwd(levels=3, tiles=tiles(HD, HD, HD)) == U
+    assert _fwd(levels=3, tiles=tiles(HD, T, T)) == U           # the tail would take level 2
+    assert _fwd(levels=2, scheme=_lib.NONSEPARABLE_LDS, tiles=tiles(HD, HD)) == U
+    assert dwt.head_levels(4096, 4096, 5) == 2                  # with the tail at levels 3..5
+    assert dwt.head_levels(7680, 4320, 5) == 2
+    assert dwt.head_levels(16384, 16384, 5) == 2
+    assert dwt.head_levels(4096, 4096, 1) == 0
+    assert dwt.head_levels(512, 512, 3) == 0                     # the tail takes every level
+    assert _lib.load().dwt2_head_levels(64, 64, 7) == _lib.ERR_INVALID_ARG

@@ -85,3 +85,34 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_launch_units_of_the_chain(bench):
+    assert bench.launch_units(5, 3, True) == [("head", 1, 2), ("tail", 3, 3)]
+    assert bench.launch_units(5, 2, True) == [("head", 1, 2), ("level", 3, 1), ("tail", 4, 2)]
+    assert bench.launch_units(5, 0, True) == [("head", 1, 2), ("level", 3, 1), ("level", 4, 1),
+                                              ("level", 5, 1)]
+    assert bench.launch_units(3, 3, False) == [("tail", 1, 3)]
+    assert bench.launch_units(2, 0, False) == [("level", 1, 1), ("level", 2, 1)]
+
+
+def test_executed_bytes_with_fused_head(bench):
+    W = H = 4096
+    lb = bench.level_bytes(W, H, 5, 4)
+    head = bench.unit_bytes(W, H, 5, 4, ("head", 1, 2))
+    # read the image once, write the detail bands of levels 1 and 2 and the
+    # level-2 LL (FP32) once: 8 bytes per image pixel, as level 1 alone
+    assert head == W * H * 4 + 3 * 4 * (2048 * 2048 + 1024 * 1024) + 1024 * 1024 * 4
+    assert head == lb[0] == 134217728
+    # the saving is the level-1 LL written and read back
+    assert lb[0] + lb[1] - head == 2 * 4 * 2048 * 2048
+    tail = bench.unit_bytes(W, H, 5, 4, ("tail", 3, 3))
+    assert tail == 8388608
+    assert bench.executed_bytes(W, H, 5, 4, 3, head=True) == head + tail
+    assert 2 * bench.executed_bytes(W, H, 5, 4, 3, head=True) / (W * H) == 17.0
+    # a single-level unit is the per-level method's level
+    for j in range(1, 6):
+        assert bench.unit_bytes(W, H, 5, 4, ("level", j, 1)) == lb[j - 1]
+    # FP16 storage: the head writes 16-bit bands and an FP32 level-2 LL
+    lb16 = bench.level_bytes(W, H, 5, 2)
+    assert bench.unit_bytes(W, H, 5, 2, ("head", 1, 2)) == lb16[0] + lb16[1] - 2 * 4 * 2048 * 2048
