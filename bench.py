@@ -500,29 +500,45 @@ def run_batch_workload(args):
         runs=runs, max_err_rel_largest_image=err)), flush=True)
 
 
+SERVE_REQUESTS = 5000          # requests per served trace
+SERVE_POOL = 256               # distinct resident inputs the requests draw from
+SERVE_BUDGET = 64 << 30        # admission budget (bytes)
+SERVE_SMALL_BUDGET = 4 << 30   # a budget small enough that admission queues
+SERVE_ITERATION_MPX = 1024     # per-iteration cap on level-input pixels (Mpx; 0: none)
+
+
+def serve_workload_text(n, dtype, cap_mpx=SERVE_ITERATION_MPX):
+    return (f"{n} requests drawn from {SERVE_POOL} resident inputs, square sides log-uniform "
+            f"in [256, 8192] (multiples of 64), levels 1..6, forward/inverse 50/50, {dtype} "
+            f"storage with FP32 intermediates, Poisson arrivals, {SERVE_BUDGET >> 30} GB "
+            f"admission budget" + (f", at most {cap_mpx:g} Mpx of level input per iteration"
+                                   if cap_mpx else ""))
+
+
 def run_serve_workload(args):
-    """Continuous batching of a Poisson stream of mixed requests: square sides
-    log-uniform in [256, 8192] (multiples of 64), 1..6 levels, forward or
-    inverse 50/50, FP16 storage with FP32 intermediates, 64 GB admission
-    budget. First the saturation throughput (every request offered at time
-    zero), then p50/p99 latency at 0.5, 0.8 and 0.95 of it."""
-    n, px, sat, sweep = serve_measure(args, args.requests, args.dtype, (0.5, 0.8, 0.95))
+    """Continuous batching of a Poisson stream of mixed requests (see
+    serve_measure): saturation throughput, then p50/p99/p99.9 latency, rate
+    and device-busy fraction at 0.5, 0.8 and 0.95 of it, and at 0.8 with a
+    4 GB admission budget."""
+    n, px, sat, sweep, small = serve_measure(args, args.requests, args.dtype, (0.5, 0.8, 0.95))
     print(json.dumps(dict(
         metric="Gpixel/s serving throughput, continuous batching of mixed requests",
         value=sat["gpixel_per_s"], unit="Gpixel/s", n_gpus=1, steps=n, warmup=n,
         ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype=args.dtype, data="synthetic",
-        config=dict(workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples "
-                             f"of 64), levels 1..6, forward/inverse 50/50, {args.dtype} storage "
-                             f"with FP32 intermediates, 64 GB admission budget",
-                    requests=n, pixels=px),
-        saturation=sat, latency_sweep=sweep)), flush=True)
+        config=dict(workload=serve_workload_text(n, args.dtype, args.serve_cap), requests=n,
+                    pixels=px,
+                    iteration_cap_mpx=args.serve_cap or None),
+        saturation=sat, latency_sweep=sweep, small_budget=small)), flush=True)
 
 
 def serve_measure(args, n, dtype, fractions):
-    """Serving runs on one seeded request set: saturation (all offered at
-    time zero) and Poisson arrivals at the given fractions of it. Returns
-    (requests, pixels, saturation, {fraction: result})."""
+    """Serving runs of n requests drawn (seeded) from a pool of SERVE_POOL
+    request shapes whose inputs are resident on the device and reused:
+    saturation (all offered at time zero), Poisson arrivals at the given
+    fractions of the saturation rate, and at 0.8 of it under a budget small
+    enough that admission queues. Returns (requests, pixels, saturation,
+    {fraction: result}, small-budget result)."""
     import numpy as np
     import torch
     import synthetic
@@ -530,48 +546,59 @@ def serve_measure(args, n, dtype, fractions):
     from paper_1705_08266_amd import serving as sv
 
     tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
-    trace = synthetic.request_stream(n, 1.0, seed=synthetic.SEED_BASE + 5)
-    reqs = [sv.Request(r.rid, 0.0, r.side, r.side, r.levels, r.inverse) for r in trace]
-    inputs = {}
-    for r, t in zip(reqs, trace):
-        x = synthetic.device_uniform_image(r.height, r.width, t.seed, tdt)
-        inputs[r.rid] = dwt.forward(x, args.wavelet, r.levels) if r.inverse else x
+    shapes = synthetic.request_stream(SERVE_POOL, 1.0, seed=synthetic.SEED_BASE + 5)
+    pool = []
+    for t in shapes:
+        x = synthetic.device_uniform_image(t.side, t.side, t.seed, tdt)
+        pool.append(dwt.forward(x, args.wavelet, t.levels) if t.inverse else x)
+    pick = np.random.default_rng(synthetic.SEED_BASE + 7).integers(0, SERVE_POOL, size=n)
+    reqs = [sv.Request(i, 0.0, shapes[k].side, shapes[k].side, shapes[k].levels,
+                       shapes[k].inverse) for i, k in enumerate(pick)]
+    inputs = {i: pool[k] for i, k in enumerate(pick)}
     torch.cuda.synchronize()
     px = sum(r.width * r.height for r in reqs)
-    print(f"[bench] serve: {n} requests, {px / 1e6:.0f} Mpx, {dtype}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] serve: {n} requests from {SERVE_POOL} inputs, {px / 1e6:.0f} Mpx, {dtype}",
+          file=sys.stderr, flush=True)
 
-    def serve(rate):
-        srv = sv.Server(budget_bytes=64 << 30, wavelet=args.wavelet, scheme=args.scheme,
-                        dtype=dtype)
+    def serve(rate, budget, sub=None):
+        rs = reqs if sub is None else reqs[:sub]
+        cap = getattr(args, "serve_cap", SERVE_ITERATION_MPX)
+        srv = sv.Server(budget_bytes=budget, wavelet=args.wavelet, scheme=args.scheme,
+                        dtype=dtype, max_iteration_pixels=int(cap * 1e6) if cap else None)
         if rate is None:
-            res = srv.run(reqs, inputs, realtime=False)
+            res = srv.run(rs, inputs, realtime=False)
         else:
             rng = np.random.default_rng(synthetic.SEED_BASE + 6)
-            t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+            t = np.cumsum(rng.exponential(1.0 / rate, size=len(rs)))
             timed = [sv.Request(r.rid, float(t[i]), r.width, r.height, r.levels, r.inverse)
-                     for i, r in enumerate(reqs)]
+                     for i, r in enumerate(rs)]
             res = srv.run(timed, inputs, realtime=True)
         torch.cuda.synchronize()
-        lat = [x.latency_s for x in res]
-        span = max(x.done_s for x in res) - min(x.arrival_s for x in res)
-        out = dict(requests_per_s=round(n / span, 1), gpixel_per_s=round(px / span / 1e9, 3),
-                   p50_ms=round(sv.percentile(lat, 50) * 1e3, 3),
-                   p99_ms=round(sv.percentile(lat, 99) * 1e3, 3),
+        sm = sv.summarize(res, lambda rid: reqs[rid].width * reqs[rid].height)
+        out = dict(requests=len(rs), completed=sm["completed"], rejected=sm["rejected"],
+                   requests_per_s=round(sm["requests_per_s"], 1),
+                   gpixel_per_s=round(sm["gpixel_per_s"], 3),
+                   p50_ms=round(sm["p50_ms"], 3), p99_ms=round(sm["p99_ms"], 3),
+                   p999_ms=round(sm["p999_ms"], 3),
+                   busy_frac=round(srv.busy_s / sm["span_s"], 4),
                    iterations=srv.iterations, launch_calls=srv.launch_calls,
-                   peak_admitted_gb=round(srv.sched.peak_used / 1e9, 2))
-        print(f"[bench] serve rate={rate}: {out}", file=sys.stderr, flush=True)
+                   peak_admitted_gb=round(srv.sched.peak_used / 1e9, 2),
+                   budget_gb=round(budget / 2**30, 1))
+        print(f"[bench] serve rate={rate} budget={budget >> 30} GB: {out}", file=sys.stderr,
+              flush=True)
         return out
 
-    serve(None)                                  # warm-up: allocator, kernel loads
-    sat = serve(None)
+    serve(None, SERVE_BUDGET, sub=min(n, 500))       # warm-up: allocator, kernel loads
+    sat = serve(None, SERVE_BUDGET)
     sweep = {}
     for f in fractions:
         sweep[str(f)] = dict(offered_per_s=round(f * sat["requests_per_s"], 1),
-                             **serve(f * sat["requests_per_s"]))
-    del inputs
+                             **serve(f * sat["requests_per_s"], SERVE_BUDGET))
+    small = dict(offered_per_s=round(0.8 * sat["requests_per_s"], 1),
+                 **serve(0.8 * sat["requests_per_s"], SERVE_SMALL_BUDGET))
+    del inputs, pool
     torch.cuda.empty_cache()
-    return n, px, sat, sweep
+    return n, px, sat, sweep, small
 
 
 def main():
@@ -597,7 +624,10 @@ def main():
                     help="skip the schemes whose every neighbour exchange goes through LDS")
     ap.add_argument("--eager", action="store_true",
                     help="launch every step from the host instead of replaying a graph")
-    ap.add_argument("--requests", type=int, default=400, help="requests in the serve workload")
+    ap.add_argument("--requests", type=int, default=SERVE_REQUESTS,
+                    help="requests in the serve workload")
+    ap.add_argument("--serve-cap", type=float, default=SERVE_ITERATION_MPX,
+                    help="serving: per-iteration cap on level-input pixels, Mpx (0: none)")
     ap.add_argument("--fuse", default="auto", choices=["auto", "off"],
                     help="auto: the library fuses the coarse levels; off: one launch per level")
     ap.add_argument("--workload", default="image", choices=["image", "batch", "serve"],
@@ -752,17 +782,23 @@ def main():
             for sch, r in ablation.items()}
 
     if not args.no_serving and (W, H, L) == (4096, 4096, 5) and args.dtype == "f32":
-        # the serving half of the metric: p50/p99 latency of the serving
-        # workload (FP16 storage) at 0.8 of its measured saturation rate
-        n, px, sat, sweep = serve_measure(args, 200, "f16", (0.8,))
+        # the serving half of the metric: the serving workload (FP16 storage),
+        # saturation, then latency at 0.5, 0.8 and 0.95 of it
+        n, px, sat, sweep, small = serve_measure(args, SERVE_REQUESTS, "f16", (0.5, 0.8, 0.95))
         at = sweep["0.8"]
         result["serving"] = dict(
-            workload=f"{n} requests, square sides log-uniform in [256, 8192] (multiples of 64), "
-                     f"levels 1..6, forward/inverse 50/50, f16 storage, 64 GB admission budget",
+            workload=serve_workload_text(n, "f16"),
             saturation_gpixel_per_s=sat["gpixel_per_s"],
             saturation_requests_per_s=sat["requests_per_s"],
             offered_per_s=at["offered_per_s"], gpixel_per_s=at["gpixel_per_s"],
-            p50_ms=at["p50_ms"], p99_ms=at["p99_ms"])
+            p50_ms=at["p50_ms"], p99_ms=at["p99_ms"], p999_ms=at["p999_ms"],
+            busy_frac=at["busy_frac"], requests=n,
+            sweep={f: {k: v[k] for k in ("offered_per_s", "requests_per_s", "gpixel_per_s",
+                                         "p50_ms", "p99_ms", "p999_ms", "busy_frac")}
+                   for f, v in sweep.items()},
+            small_budget={k: small[k] for k in ("budget_gb", "offered_per_s", "requests_per_s",
+                                                "p50_ms", "p99_ms", "p999_ms",
+                                                "peak_admitted_gb")})
 
     x_stored = main_run["stored"].astype(np.float64)
     scale = float(np.abs(x_stored).max())

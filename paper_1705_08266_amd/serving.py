@@ -24,6 +24,8 @@ from __future__ import annotations
 import collections
 import ctypes
 import dataclasses
+import fractions
+import math
 import time
 
 from . import _lib
@@ -73,21 +75,35 @@ class _Active:
         self.payload = None
 
 
+def level_pixels(req: Request, level: int) -> int:
+    """Input pixels of a request's level-th launch (0-based, in execution
+    order: the forward starts at the full image, the inverse at the coarsest
+    level)."""
+    j = req.levels - level if req.inverse else level + 1
+    return (req.width >> (j - 1)) * (req.height >> (j - 1))
+
+
 class Scheduler:
     """FIFO admission under a byte budget and a cap on active requests;
-    level-synchronous iterations.
+    level-synchronous iterations, optionally capped in work.
 
     offer(req)        queue an arrived request (False if it can never fit)
     admit(now)        move queue heads into the active set while they fit
-    iteration()       the active requests to advance by one level now
+    iteration()       the active requests to advance by one level now: all of
+                      them, or with max_iteration_pixels the oldest ones whose
+                      level inputs add up to at most that many pixels (always
+                      at least the oldest), so that one iteration's device
+                      time stays bounded however many requests are admitted
     finish_iteration  advance them; returns those that have enqueued their
                       last level (their bytes stay held until release())
     release(a)        return a finished request's bytes to the budget
     """
 
-    def __init__(self, budget_bytes: int, max_active: int = 1 << 30, bytes_fn=request_bytes):
+    def __init__(self, budget_bytes: int, max_active: int = 1 << 30, bytes_fn=request_bytes,
+                 max_iteration_pixels: int | None = None):
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
+        self.max_iteration_pixels = max_iteration_pixels
         self.bytes_fn = bytes_fn
         self.queue = collections.deque()
         self.active = []
@@ -118,7 +134,16 @@ class Scheduler:
         return admitted
 
     def iteration(self):
-        return list(self.active)
+        if self.max_iteration_pixels is None:
+            return list(self.active)
+        out, px = [], 0
+        for a in self.active:                  # admission order: oldest first
+            p = level_pixels(a.req, a.next_level)
+            if out and px + p > self.max_iteration_pixels:
+                break
+            out.append(a)
+            px += p
+        return out
 
     def finish_iteration(self, advanced):
         done = []
@@ -201,12 +226,31 @@ def level_jobs(src, out, ws0, ws1, levels, inverse):
 class Result:
     rid: int
     arrival_s: float
-    done_s: float          # GPU completion time, same clock as arrival_s
+    done_s: float          # GPU completion time, same clock as arrival_s (NaN if rejected)
     output: object         # the output tensor (None once released by the server)
+    rejected: bool = False  # refused at arrival: it can never fit the admission budget
 
     @property
     def latency_s(self) -> float:
         return self.done_s - self.arrival_s
+
+
+def summarize(results, pixels_of) -> dict:
+    """Throughput and latency of one served trace. Rejected requests count
+    only in `rejected`: they have no completion time and take no part in the
+    latency percentiles, the span or the throughput. pixels_of(rid) gives a
+    request's image pixels."""
+    done = [r for r in results if not r.rejected]
+    out = dict(completed=len(done), rejected=len(results) - len(done))
+    if not done:
+        return out
+    lat = [r.latency_s for r in done]
+    span = max(r.done_s for r in done) - min(r.arrival_s for r in done)
+    px = sum(pixels_of(r.rid) for r in done)
+    out.update(span_s=span, requests_per_s=len(done) / span, gpixel_per_s=px / span / 1e9,
+               p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3,
+               p999_ms=percentile(lat, 99.9) * 1e3)
+    return out
 
 
 class Server:
@@ -220,10 +264,12 @@ class Server:
     """
 
     def __init__(self, budget_bytes=64 << 30, max_active=1 << 30, wavelet="cdf97",
-                 scheme="nonseparable", dtype="f16", class_tiles=None, max_inflight=2):
+                 scheme="nonseparable", dtype="f16", class_tiles=None, max_inflight=2,
+                 max_iteration_pixels=None):
         self.dtype = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[dtype]
         self.sched = Scheduler(budget_bytes, max_active,
-                               bytes_fn=lambda r: request_bytes(r, self.dtype))
+                               bytes_fn=lambda r: request_bytes(r, self.dtype),
+                               max_iteration_pixels=max_iteration_pixels)
         self.wavelet = _wavelet(wavelet)
         self.scheme = _scheme(scheme)
         self.class_tiles = (None if class_tiles is None else
@@ -231,6 +277,7 @@ class Server:
         self.max_inflight = max_inflight
         self.iterations = 0
         self.launch_calls = 0
+        self.busy_s = 0.0           # summed device time of the iterations (see run)
 
     def _allocate(self, a, inputs, torch):
         req = a.req
@@ -269,15 +316,19 @@ class Server:
         stream = torch.cuda.current_stream()
         sptr = _stream_ptr(stream)
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
-        inflight = collections.deque()          # (event, finished actives)
+        inflight = collections.deque()          # (start event, end event, finished actives)
         results = []
         start = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         start.record(stream)
 
-        def retire(ev, done):
+        def retire(ev0, ev, done):
             ms = start.elapsed_time(ev)
+            # an iteration's device time: from the stream reaching its launches
+            # to their end (when the device was idle before it, this includes
+            # the host's launch latency: an upper bound)
+            self.busy_s += ev0.elapsed_time(ev) / 1e3
             for a in done:
                 out = a.payload["out"]
                 results.append(Result(a.req.rid, a.req.arrival_s if realtime else 0.0,
@@ -290,23 +341,26 @@ class Server:
             while pending and (not realtime or pending[0].arrival_s <= now):
                 r = pending.popleft()
                 if not self.sched.offer(r):            # can never fit the budget
-                    results.append(Result(r.rid, r.arrival_s, float("nan"), None))
+                    results.append(Result(r.rid, r.arrival_s, float("nan"), None,
+                                          rejected=True))
             for a in self.sched.admit(now):
                 self._allocate(a, inputs, torch)
             advanced = self.sched.iteration()
             if advanced:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
                 self._enqueue(advanced, sptr)
                 done = self.sched.finish_iteration(advanced)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(stream)
-                inflight.append((ev, done))
+                inflight.append((ev0, ev, done))
                 self.iterations += 1
             # observe completions; keep at most max_inflight iterations queued
-            while inflight and (len(inflight) > self.max_inflight or inflight[0][0].query()
+            while inflight and (len(inflight) > self.max_inflight or inflight[0][1].query()
                                 or (not advanced and not pending)):
-                ev, done = inflight.popleft()
+                ev0, ev, done = inflight.popleft()
                 ev.synchronize()
-                retire(ev, done)
+                retire(ev0, ev, done)
             if not advanced and not inflight and pending and realtime:
                 wait = pending[0].arrival_s - (time.perf_counter() - t0)
                 if wait > 0:
@@ -315,7 +369,8 @@ class Server:
 
 
 def percentile(values, q):
-    """Nearest-rank percentile (q in 0..100) of a non-empty list."""
+    """Nearest-rank percentile (q in 0..100) of a non-empty list: the
+    ceil(q/100 * n)-th smallest value."""
     v = sorted(values)
-    k = max(0, min(len(v) - 1, int(-(-q * len(v) // 100)) - 1))
-    return v[k]
+    rank = math.ceil(fractions.Fraction(str(q)) * len(v) / 100)   # exact for q = 99.9
+    return v[max(0, min(len(v) - 1, rank - 1))]

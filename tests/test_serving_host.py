@@ -165,3 +165,67 @@ def test_percentile_nearest_rank():
     assert sv.percentile(v, 100) == 100
     assert sv.percentile([3.0], 99) == 3.0
     assert math.isclose(sv.percentile(np.linspace(0, 1, 11).tolist(), 50), 0.5)
+
+
+def test_percentile_is_exact_at_99_9():
+    v = list(range(1, 1001))
+    assert sv.percentile(v, 99.9) == 999          # ceil(0.999 * 1000) = 999, not 1000
+    assert sv.percentile(v, 99) == 990
+    assert sv.percentile(list(range(1, 5001)), 99.9) == 4995
+
+
+def test_summary_leaves_rejected_requests_out():
+    """A request refused at arrival has no completion time: it must not reach
+    the percentiles, the span or the throughput, only the rejected count."""
+    R = sv.Result
+    res = [R(0, 0.0, 0.010, None), R(1, 0.001, 0.004, None),
+           R(2, 0.002, float("nan"), None, rejected=True), R(3, 0.003, 0.012, None)]
+    s = sv.summarize(res, lambda rid: 100)
+    assert s["completed"] == 3 and s["rejected"] == 1
+    assert s["span_s"] == pytest.approx(0.012)
+    assert s["requests_per_s"] == pytest.approx(3 / 0.012)
+    assert s["gpixel_per_s"] == pytest.approx(300 / 0.012 / 1e9)
+    lat = sorted([0.010, 0.003, 0.009])
+    assert s["p50_ms"] == pytest.approx(lat[1] * 1e3)
+    assert s["p99_ms"] == pytest.approx(lat[2] * 1e3)
+    assert all(not math.isnan(v) for v in s.values())
+    assert sv.summarize([R(5, 0.0, float("nan"), None, rejected=True)], lambda r: 1) == \
+        dict(completed=0, rejected=1)
+
+
+def test_budget_too_small_rejects_at_arrival():
+    """With a budget below one request's bytes the scheduler refuses it at
+    offer time; requests that fit still queue and run in FIFO order."""
+    big = sv.Request(0, 0.0, 2048, 2048, 3, False)
+    small = sv.Request(1, 0.0, 256, 256, 2, True)
+    budget = sv.request_bytes(small) * 2
+    assert sv.request_bytes(big) > budget
+    sch = sv.Scheduler(budget)
+    assert sch.offer(big) is False and sch.rejected == [big]
+    assert sch.offer(small) is True
+    assert [a.req.rid for a in sch.admit(0.0)] == [1]
+
+
+def test_iteration_pixel_cap_advances_the_oldest_first():
+    reqs = [sv.Request(0, 0.0, 1024, 1024, 2, False),     # level inputs 1024^2, 512^2
+            sv.Request(1, 0.0, 512, 512, 3, True),        # inverse: 128^2, 256^2, 512^2
+            sv.Request(2, 0.0, 2048, 2048, 1, False)]
+    assert [sv.level_pixels(reqs[1], k) for k in range(3)] == [128 * 128, 256 * 256, 512 * 512]
+    assert [sv.level_pixels(reqs[0], k) for k in range(2)] == [1024 * 1024, 512 * 512]
+    sch = sv.Scheduler(1 << 40, max_iteration_pixels=1024 * 1024 + 128 * 128)
+    for r in reqs:
+        sch.offer(r)
+    sch.admit(0.0)
+    it = sch.iteration()
+    assert [a.req.rid for a in it] == [0, 1]              # request 2 would exceed the cap
+    sch.finish_iteration(it)
+    it = sch.iteration()
+    assert [a.req.rid for a in it] == [0, 1]              # 512^2 + 256^2 leave no room for 2048^2
+    done = sch.finish_iteration(it)
+    assert [a.req.rid for a in done] == [0]
+    it = sch.iteration()
+    assert [a.req.rid for a in it] == [1]                 # 512^2 + 2048^2 > cap: oldest only
+    sch.finish_iteration(it)
+    it = sch.iteration()
+    assert [a.req.rid for a in it] == [2]                 # alone it may exceed the cap
+    assert sv.Scheduler(1 << 40).max_iteration_pixels is None
