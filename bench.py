@@ -336,6 +336,146 @@ def run_gpu(args, x_np, scheme):
     return out
 
 
+AB_STEPS = 200     # single steps per scheme in the interleaved comparison
+AB_ROUNDS = 10     # alternations of the per-launch timing loops
+
+
+def ab_schemes(args, x_np):
+    """Non-separable against separable lifting, interleaved in one process on
+    the same buffers: single-step graph replays alternate between the two
+    schemes (the order swapping every step) for AB_STEPS steps each, and the
+    per-launch timing loops (20 back-to-back launches of each chain launch)
+    alternate AB_ROUNDS times. Returns medians and p10 / p90 of both."""
+    import numpy as np
+    import torch
+    import paper_1705_08266_amd as dwt
+    from paper_1705_08266_amd import _lib
+
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    H, W = x_np.shape
+    L = args.levels
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(x_np).to(dev).to(tdt)
+    sets = [(x0.clone(), torch.empty_like(x0), torch.empty_like(x0),
+             dwt.make_workspace(W, H, L, dev)) for _ in range(buffer_sets(args, W, H))]
+    schemes = ("nonseparable", "separable")
+    stream = torch.cuda.current_stream()
+
+    def step(k, sch):
+        src, coef, rec, ws = sets[k % len(sets)]
+        dwt.forward(src, args.wavelet, L, sch, out=coef, workspace=ws)
+        dwt.inverse(coef, args.wavelet, L, sch, out=rec, workspace=ws)
+
+    graphs = {}
+    for sch in schemes:
+        for k in range(3):
+            step(k, sch)
+        torch.cuda.synchronize()
+        graphs[sch] = []
+        for k in range(len(sets)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(k, sch)
+            graphs[sch].append(g)
+    for k in range(2 * len(sets)):
+        for sch in schemes:
+            graphs[sch][k % len(sets)].replay()
+    torch.cuda.synchronize()
+    ev = {sch: [] for sch in schemes}
+    for k in range(AB_STEPS):
+        order = schemes if k % 2 == 0 else schemes[::-1]
+        for sch in order:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            graphs[sch][k % len(sets)].replay()
+            b.record(stream)
+            ev[sch].append((a, b))
+    torch.cuda.synchronize()
+    step_ms = {sch: np.array([a.elapsed_time(b) for a, b in ev[sch]]) for sch in schemes}
+
+    # per-launch loops: the chain's launches (head / levels / tail), 20 each
+    fused = dwt.fused_levels(W, H, L)
+    units = launch_units(L, fused, dwt.head_levels(W, H, L) == 2)
+
+    def launch(unit, direction, k, sch):
+        kind, j, n = unit
+        src, coef, rec, ws = sets[k % len(sets)]
+        w, h = W >> (j - 1), H >> (j - 1)
+        if kind == "level" and j > 1:
+            img = ws[:w * h].view(h, w)
+            if direction == "forward":
+                dwt.forward(img, args.wavelet, 1, sch, out=coef[:h, :w])
+            else:
+                dwt.inverse(coef[:h, :w], args.wavelet, 1, sch, out=img)
+            return
+        if kind == "tail" and j > 1:
+            img = ws[:w * h].view(h, w)
+            tws = tail_ws[unit]
+            if direction == "forward":
+                dwt.forward(img, args.wavelet, n, sch, out=coef[:h, :w], workspace=tws,
+                            tiles=[_lib.TILE_TAIL] * n)
+            else:
+                dwt.inverse(coef[:h, :w], args.wavelet, n, sch, out=img, workspace=tws,
+                            tiles=[_lib.TILE_TAIL] * n)
+            return
+        tiles = [_lib.TILE_HEAD] * 2 if kind == "head" else \
+            ([_lib.TILE_TAIL] * n if kind == "tail" else None)
+        if direction == "forward":
+            dwt.forward(src, args.wavelet, n, sch, out=coef, workspace=ws, tiles=tiles)
+        else:
+            dwt.inverse(coef, args.wavelet, n, sch, out=rec, workspace=ws, tiles=tiles)
+
+    tail_ws = {u: dwt.make_workspace(W >> (u[1] - 1), H >> (u[1] - 1), u[2], dev)
+               for u in units if u[0] == "tail"}
+    loops = {}
+    for sch in schemes:
+        for u in units:
+            for direction in ("forward", "inverse"):
+                for k in range(3):
+                    launch(u, direction, k, sch)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    for k in range(20):
+                        launch(u, direction, k, sch)
+                loops[(sch, u, direction)] = g
+    torch.cuda.synchronize()
+    per = {key: [] for key in loops}
+    for r in range(AB_ROUNDS):
+        order = schemes if r % 2 == 0 else schemes[::-1]
+        for sch in order:
+            for u in units:
+                for direction in ("forward", "inverse"):
+                    g = loops[(sch, u, direction)]
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    g.replay()
+                    b.record(stream)
+                    torch.cuda.synchronize()
+                    per[(sch, u, direction)].append(a.elapsed_time(b) / 20)
+
+    def stats(v):
+        v = np.asarray(v)
+        return dict(median=round(float(np.median(v)), 5), p10=round(float(np.percentile(v, 10)), 5),
+                    p90=round(float(np.percentile(v, 90)), 5))
+
+    out = {"protocol": f"{AB_STEPS} single-step graph replays per scheme, alternating A/B "
+                       f"(order swapped every step), then {AB_ROUNDS} alternating rounds of "
+                       f"20-launch loops per chain launch; same buffers, same process"}
+    for sch in schemes:
+        out[sch] = dict(step_ms=stats(step_ms[sch]),
+                        gpixel_s_at_median=round(W * H / (np.median(step_ms[sch]) * 1e-3) / 1e9, 3),
+                        launch_ms={f"{u[0]} {u[1]}" + (f"-{u[1] + u[2] - 1}" if u[2] > 1 else "")
+                                   + f" {d}": stats(per[(sch, u, d)])
+                                   for u in units for d in ("forward", "inverse")})
+    diff = step_ms["nonseparable"] - step_ms["separable"]   # paired by step index
+    out["step_ms_nonseparable_minus_separable"] = stats(diff)
+    del sets, graphs, loops
+    torch.cuda.empty_cache()
+    return out
+
+
 def load_traffic(kernel_key: str):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -679,6 +819,11 @@ def main():
         print("[bench] separable-lifting kernel, same protocol", file=sys.stderr, flush=True)
         sep_run = run_gpu(args, x, "separable")
 
+    ab = None
+    if not args.no_separable and args.scheme == "nonseparable":
+        print("[bench] interleaved A/B: non-separable vs separable", file=sys.stderr, flush=True)
+        ab = ab_schemes(args, x)
+
     ablation = {}
     if not args.no_ablation and args.dtype == "f32" and args.scheme in ("nonseparable", "separable"):
         # both schemes with every neighbour exchange through LDS and a barrier
@@ -771,6 +916,9 @@ def main():
                                    / (s1 * 1e-3) / 1e9, 1),
             launch_ms=dict(forward=rounded(sep_run["fwd_level_ms"]),
                            inverse=rounded(sep_run["inv_level_ms"])))
+
+    if ab is not None:
+        result["scheme_ab"] = ab
 
     if ablation:
         result["exchange_ablation"] = {
