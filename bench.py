@@ -41,7 +41,7 @@ METRIC = ("Gpixel/s fwd+inv CDF 9/7 DWT at 4096², 5 levels (% HBM peak); "
           "serving p50/p99")
 # Traffic counters are valid for the kernel code they were taken with (these
 # sources) and the tile geometry named in their key.
-KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp")
+KERNEL_SOURCES = ("dwt2_device.hpp", "dwt2_kernels.hpp", "dwt2_head.hpp", "dwt2_tail.hpp")
 
 
 def kernel_source_sha() -> str:
