@@ -162,67 +162,77 @@ def run_gpu(args, x_np, scheme):
     eager_coef = sets[0][1].clone()
     eager_rec = sets[0][2].clone()
 
+    # one captured graph per buffer set (the whole L-level forward and inverse
+    # chain), and one graph that holds a step on every buffer set
     graphs = []
-    if not args.eager:
-        # one captured graph per buffer set: the whole L-level forward and
-        # inverse chain is replayed as one launch
+    for k in range(len(sets)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(k)
+        graphs.append(g)
+    multi = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(multi):
         for k in range(len(sets)):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                step(k)
-            graphs.append(g)
-        for k in range(2 * len(sets)):
-            graphs[k % len(sets)].replay()
-        torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    K = args.steps
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+            step(k)
+    for k in range(2 * len(sets)):
+        graphs[k % len(sets)].replay()
+    multi.replay()
     torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t_start.record(stream)
-    for k in range(K):
-        if graphs:
+
+    # The timed steps: host calls of the library by default, as a caller makes
+    # them (a graph launch costs a few microseconds of its own on this stack);
+    # --graph replays the per-step graphs instead.
+    def run_step(k):
+        if args.graph:
             graphs[k % len(graphs)].replay()
         else:
             step(k)
-    t_end.record(stream)
-    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    K = args.steps
+
+    def timed_ms(fn, n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for k in range(n):
+            fn(k)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    w0 = time.perf_counter()
+    total_ms = timed_ms(run_step, K)
     wall = time.perf_counter() - w0
-    total_ms = t_start.elapsed_time(t_end)
+
+    # the same K steps as graph replays: one graph per step, and graphs of
+    # len(sets) steps each (the last writes every buffer set)
+    graph_ms = dict(per_step=timed_ms(lambda k: graphs[k % len(graphs)].replay(), K) / K,
+                    multi_step=timed_ms(lambda k: multi.replay(), max(1, K // len(sets)))
+                    / (max(1, K // len(sets)) * len(sets)),
+                    steps_per_graph=len(sets))
     replay_matches = bool(torch.equal(sets[0][1], eager_coef) and torch.equal(sets[0][2], eager_rec))
 
-    # Spread of single steps: each replay bracketed by its own events (cold
-    # buffers, rotating as above).
-    step_ms = []
-    if graphs:
-        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                 for _ in range(STEP_SAMPLES)]
-        for k, (a, b) in enumerate(pairs):
-            a.record(stream)
-            graphs[k % len(graphs)].replay()
-            b.record(stream)
-        torch.cuda.synchronize()
-        step_ms = sorted(a.elapsed_time(b) for a, b in pairs)
+    # Spread of single steps: each bracketed by its own events (cold buffers,
+    # rotating as above).
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(STEP_SAMPLES)]
+    for k, (a, b) in enumerate(pairs):
+        a.record(stream)
+        run_step(k)
+        b.record(stream)
+    torch.cuda.synchronize()
+    step_ms = sorted(a.elapsed_time(b) for a, b in pairs)
 
     # Warm cache: the same buffer set every step, so the image and its
     # coefficients stay in the Infinity Cache.
-    warm_ms = None
-    if graphs:
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        graphs[0].replay()
-        a.record(stream)
-        for _ in range(K):
-            graphs[0].replay()
-        b.record(stream)
-        torch.cuda.synchronize()
-        warm_ms = a.elapsed_time(b) / K
+    run_step(0)
+    warm_ms = timed_ms(lambda k: run_step(0), K) / K
 
     # The same K steps with consecutive steps (independent buffer sets) on two
     # streams, so that one chain's launch gaps overlap the other's kernels.
     concurrent_ms = None
-    if graphs and len(graphs) >= 2:
+    if len(graphs) >= 2:
         side = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
         for _ in range(2):
             c0 = torch.cuda.Event(enable_timing=True)
@@ -330,8 +340,8 @@ def run_gpu(args, x_np, scheme):
                units=units, fused_levels=list(range(L - fused + 1, L + 1)) if fused else [],
                head=head,
                coef=eager_coef.float().cpu().numpy(), rec=eager_rec.float().cpu().numpy(),
-               stored=sets[0][0].float().cpu().numpy(), graph=bool(graphs),
-               replay_matches_eager=replay_matches)
+               stored=sets[0][0].float().cpu().numpy(),
+               replay_matches_eager=replay_matches, graph=args.graph, graph_ms=graph_ms)
     del sets, graphs
     torch.cuda.empty_cache()
     return out
@@ -343,8 +353,8 @@ AB_ROUNDS = 10     # alternations of the per-launch timing loops
 
 def ab_schemes(args, x_np):
     """Non-separable against separable lifting, interleaved in one process on
-    the same buffers: single-step graph replays alternate between the two
-    schemes (the order swapping every step) for AB_STEPS steps each, and the
+    the same buffers: single steps (host calls, as in the timed loop) alternate
+    between the two schemes (the order swapping every step) for AB_STEPS steps each, and the
     per-launch timing loops (20 back-to-back launches of each chain launch)
     alternate AB_ROUNDS times. Returns medians and p10 / p90 of both."""
     import numpy as np
@@ -367,20 +377,9 @@ def ab_schemes(args, x_np):
         dwt.forward(src, args.wavelet, L, sch, out=coef, workspace=ws)
         dwt.inverse(coef, args.wavelet, L, sch, out=rec, workspace=ws)
 
-    graphs = {}
-    for sch in schemes:
-        for k in range(3):
-            step(k, sch)
-        torch.cuda.synchronize()
-        graphs[sch] = []
-        for k in range(len(sets)):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                step(k, sch)
-            graphs[sch].append(g)
     for k in range(2 * len(sets)):
         for sch in schemes:
-            graphs[sch][k % len(sets)].replay()
+            step(k, sch)
     torch.cuda.synchronize()
     ev = {sch: [] for sch in schemes}
     for k in range(AB_STEPS):
@@ -389,7 +388,7 @@ def ab_schemes(args, x_np):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            graphs[sch][k % len(sets)].replay()
+            step(k, sch)
             b.record(stream)
             ev[sch].append((a, b))
     torch.cuda.synchronize()
@@ -465,7 +464,7 @@ def ab_schemes(args, x_np):
         return dict(median=round(float(np.median(v)), 5), p10=round(float(np.percentile(v, 10)), 5),
                     p90=round(float(np.percentile(v, 90)), 5))
 
-    out = {"protocol": f"{AB_STEPS} single-step graph replays per scheme, alternating A/B "
+    out = {"protocol": f"{AB_STEPS} single steps (host calls) per scheme, alternating A/B "
                        f"(order swapped every step), then (FP32 storage) {AB_ROUNDS} alternating "
                        f"rounds of 20-launch loops per chain launch; same buffers, same process"}
     for sch in schemes:
@@ -476,7 +475,7 @@ def ab_schemes(args, x_np):
                                    for u in units for d in ("forward", "inverse")})
     diff = step_ms["nonseparable"] - step_ms["separable"]   # paired by step index
     out["step_ms_nonseparable_minus_separable"] = stats(diff)
-    del sets, graphs, loops
+    del sets, loops
     torch.cuda.empty_cache()
     return out
 
@@ -655,7 +654,7 @@ SERVE_ITERATION_MPX = 1024     # per-iteration cap on level-input pixels (Mpx; 0
 def serve_workload_text(n, dtype, cap_mpx=SERVE_ITERATION_MPX):
     return (f"{n} requests drawn from {SERVE_POOL} resident inputs, square sides log-uniform "
             f"in [256, 8192] (multiples of 64), levels 1..6, forward/inverse 50/50, {dtype} "
-            f"storage with FP32 intermediates, Poisson arrivals, {SERVE_BUDGET >> 30} GB "
+            f"storage with FP32 intermediates, Poisson arrivals, {SERVE_BUDGET >> 30} GiB "
             f"admission budget" + (f", at most {cap_mpx:g} Mpx of level input per iteration"
                                    if cap_mpx else ""))
 
@@ -664,7 +663,7 @@ def run_serve_workload(args):
     """Continuous batching of a Poisson stream of mixed requests (see
     serve_measure): saturation throughput, then p50/p99/p99.9 latency, rate
     and device-busy fraction at 0.5, 0.8 and 0.95 of it, and at 0.8 with a
-    4 GB admission budget."""
+    4 GiB admission budget."""
     n, px, sat, sweep, small = serve_measure(args, args.requests, args.dtype, (0.5, 0.8, 0.95))
     print(json.dumps(dict(
         metric="Gpixel/s serving throughput, continuous batching of mixed requests",
@@ -727,9 +726,9 @@ def serve_measure(args, n, dtype, fractions):
                    p999_ms=round(sm["p999_ms"], 3),
                    busy_frac=round(srv.busy_s / sm["span_s"], 4),
                    iterations=srv.iterations, launch_calls=srv.launch_calls,
-                   peak_admitted_gb=round(srv.sched.peak_used / 1e9, 2),
-                   budget_gb=round(budget / 2**30, 1))
-        print(f"[bench] serve rate={rate} budget={budget >> 30} GB: {out}", file=sys.stderr,
+                   peak_admitted_gib=round(srv.sched.peak_used / 2**30, 2),
+                   budget_gib=round(budget / 2**30, 1))
+        print(f"[bench] serve rate={rate} budget={budget >> 30} GiB: {out}", file=sys.stderr,
               flush=True)
         return out
 
@@ -767,8 +766,8 @@ def main():
                     help="skip the serving latency measurement of the default workload")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the schemes whose every neighbour exchange goes through LDS")
-    ap.add_argument("--eager", action="store_true",
-                    help="launch every step from the host instead of replaying a graph")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of one captured graph per step instead of host calls")
     ap.add_argument("--requests", type=int, default=SERVE_REQUESTS,
                     help="requests in the serve workload")
     ap.add_argument("--serve-cap", type=float, default=SERVE_ITERATION_MPX,
@@ -898,8 +897,17 @@ def main():
                        inverse=rounded(main_run["inv_level_ms"])),
         fused_levels=dict(head=[1, 2] if main_run["head"] else [],
                           tail=main_run["fused_levels"]),
-        launch=("one captured HIP graph per buffer set (forward + inverse chain)"
-                if main_run["graph"] else "eager launches"),
+        launch=("one captured HIP graph per step (forward + inverse chain)"
+                if main_run["graph"] else "host calls of the library on one stream"),
+        graph_replay=dict(
+            per_step=dict(value=round(W * H / (main_run["graph_ms"]["per_step"] * 1e-3) / 1e9, 3),
+                          ms_per_step=round(main_run["graph_ms"]["per_step"], 5)),
+            multi_step=dict(value=round(W * H / (main_run["graph_ms"]["multi_step"] * 1e-3) / 1e9,
+                                        3),
+                            ms_per_step=round(main_run["graph_ms"]["multi_step"], 5),
+                            steps_per_graph=main_run["graph_ms"]["steps_per_graph"]),
+            note="the same steps replayed from captured graphs: one graph per step, or one "
+                 "graph holding a step on every buffer set"),
         two_streams=(None if main_run["concurrent_ms"] is None else dict(
             value=round(W * H / (main_run["concurrent_ms"] / K * 1e-3) / 1e9, 3),
             ms_per_step=round(main_run["concurrent_ms"] / K, 5),
@@ -954,9 +962,9 @@ def main():
             sweep={f: {k: v[k] for k in ("offered_per_s", "requests_per_s", "gpixel_per_s",
                                          "p50_ms", "p99_ms", "p999_ms", "busy_frac")}
                    for f, v in sweep.items()},
-            small_budget={k: small[k] for k in ("budget_gb", "offered_per_s", "requests_per_s",
+            small_budget={k: small[k] for k in ("budget_gib", "offered_per_s", "requests_per_s",
                                                 "p50_ms", "p99_ms", "p999_ms",
-                                                "peak_admitted_gb")})
+                                                "peak_admitted_gib")})
 
     x_stored = main_run["stored"].astype(np.float64)
     scale = float(np.abs(x_stored).max())
