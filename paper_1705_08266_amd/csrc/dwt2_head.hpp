@@ -70,8 +70,21 @@ struct InvHead {
 // Position p of an LDS axis of n values starting at p0, clamped into it.
 __device__ __forceinline__ int lds_at(int p, int p0, int n) { return min(max(p - p0, 0), n - 1); }
 
+// Wavefronts per SIMD that the register allocation must allow. Two head
+// workgroups share a CU (their LDS fits twice), which takes WAVES/2 per SIMD,
+// i.e. at most 80 VGPRs for 12 wavefronts. Left free, the separable forward
+// head with 16-bit input comes out at 81 and runs one workgroup per CU (about
+// 35% slower); that instantiation is held to the budget. The others fit as they
+// are and keep the allocation the workgroup size alone implies.
+template <int SCH, int WAVES, typename TIN>
+constexpr int kFwdHeadWavesPerSimd =
+    (SCH == SEP && sizeof(TIN) == 2) ? (2 * WAVES + 3) / 4 : (WAVES + 3) / 4;
+template <int WAVES>
+constexpr int kInvHeadWavesPerSimd = (WAVES + 3) / 4;
+
 template <int WV, int SCH, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
-__global__ __launch_bounds__(64 * WAVES) void fwd_head_kernel(FwdHead hd) {
+__global__ __launch_bounds__(64 * WAVES, (kFwdHeadWavesPerSimd<SCH, WAVES, TIN>)) void fwd_head_kernel(
+    FwdHead hd) {
     using G = HeadGeom<ROWS, WAVES>;
     using L = Wavelet<WV>;
     constexpr int RG = G::RG, H2 = G::FH2, R2 = G::FROWS2, NR1 = G::NR1;
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(64 * WAVES) void fwd_head_kernel(FwdHead hd) {
 }
 
 template <int WV, int SCH, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
-__global__ __launch_bounds__(64 * WAVES) void inv_head_kernel(InvHead hd) {
+__global__ __launch_bounds__(64 * WAVES, kInvHeadWavesPerSimd<WAVES>) void inv_head_kernel(InvHead hd) {
     using G = HeadGeom<ROWS, WAVES>;
     using L = Wavelet<WV>;
     constexpr int RG = G::RG, H2 = G::IH2, R2 = G::IROWS2, NR1 = G::NR1;
