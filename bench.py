@@ -570,8 +570,11 @@ def run_batch_workload(args):
     """256 uneven images (sides log-uniform in [64, 4096], multiples of 32),
     3-level forward, planned once: each level is one launch over all images
     per tile configuration in use, captured in one graph. Times the default
-    tiles with one workgroup per tile and with a persistent grid, then the
-    per-class tuned tiles with the faster grid."""
+    tiles with one workgroup per tile and with a persistent grid, the
+    per-class tuned tiles with the faster grid, then levels 1 and 2 fused into
+    one head launch over all images (both grids) with the tuned tiles after.
+    The spot parity check runs on the last plan's outputs. hbm_frac counts the
+    per-level method's bytes throughout."""
     import numpy as np
     import torch
     import synthetic
@@ -622,6 +625,20 @@ def run_batch_workload(args):
     runs["tuned_tiles"] = dict(ms=round(ms_tuned, 5), grid=grid, class_tiles=class_tiles,
                                gpixel_s=round(plan.pixels / ms_tuned / 1e6, 3),
                                launches_per_level=plan.launches()[1])
+    if L >= 2:
+        # levels 1 and 2 of every image in one head launch, the tuned tiles
+        # for the levels after
+        for name, persistent in (("head_one_workgroup_per_tile", False), ("head_persistent", True)):
+            del plan
+            plan = BatchPlan.forward(imgs, L, args.wavelet, args.scheme, class_tiles, persistent,
+                                     fuse_head=True)
+            ms_h = time_plan(plan)
+            runs[name] = dict(ms=round(ms_h, 5), class_tiles=class_tiles,
+                              gpixel_s=round(plan.pixels / ms_h / 1e6, 3),
+                              hbm_frac=round(alg / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              launches_per_level=plan.launches()[1])
+            print(f"[bench] head + tuned tiles, {name}: {ms_h:.4f} ms", file=sys.stderr,
+                  flush=True)
     best = min(runs.values(), key=lambda r: r["ms"])
     ms = best["ms"]
     px = plan.pixels

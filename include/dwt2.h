@@ -257,7 +257,9 @@ int dwt2_default_tile(int32_t width, int32_t height, dwt2_wavelet wavelet,
  * Many images of one storage type, wavelet and level count, planned once and
  * run as few launches: each level is one launch over every image whose size
  * class uses the same tile configuration (one launch per level with the
- * default configurations of FP32 storage). Not a topic of the paper, which
+ * default configurations of FP32 storage), and with DWT2_PLAN_HEAD levels 1
+ * and 2 are one launch over every image (fusing consecutive levels, Sec. 5,
+ * as the default chain of dwt2_forward does). Not a topic of the paper, which
  * transforms one image at a time: batching serves many uneven images.
  *
  * dwt2_batch_plan writes a plan (a byte image in host memory, of
@@ -288,25 +290,34 @@ typedef struct {
  * for sizes below 2. */
 int dwt2_size_class(int32_t width, int32_t height);
 
+/* Plan flag: with two or more levels, levels 1 and 2 of every image run as
+ * one launch of the fused head (the level-1 low-low band stays on chip, as in
+ * dwt2_forward's default chain), planned at level 1; the tile configurations
+ * then serve levels 3 and beyond. No effect with one level. */
+#define DWT2_PLAN_HEAD 1
+
 /* Bytes of the plan of an L-level forward (inverse = 0) or inverse
  * (inverse = 1) transform of images[0..n), n >= 1, in *bytes. Each image is
  * checked as by dwt2_forward (dwt2_inverse); src and dst of one image must
  * not overlap, and no image may write a buffer another image reads or writes
  * (images may share a source). class_tiles: NULL for the library's choice,
  * else DWT2_SIZE_CLASSES tile configuration ids, the one used for the levels
- * of each size class. Returns a dwt2_status. */
+ * of each size class. flags: 0 or DWT2_PLAN_HEAD (others:
+ * DWT2_ERR_UNSUPPORTED). Returns a dwt2_status. */
 int dwt2_batch_plan_bytes(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
                           dwt2_wavelet wavelet, int32_t levels, int32_t inverse,
-                          dwt2_boundary boundary, const int32_t *class_tiles, size_t *bytes);
+                          dwt2_boundary boundary, const int32_t *class_tiles, int32_t flags,
+                          size_t *bytes);
 
 /* Writes the plan into plan[0..plan_bytes) (host memory): DWT2_ERR_WORKSPACE
  * if plan_bytes is too small, else as dwt2_batch_plan_bytes. */
 int dwt2_batch_plan(const dwt2_image *images, int32_t n, dwt2_dtype dtype, dwt2_wavelet wavelet,
                     int32_t levels, int32_t inverse, dwt2_boundary boundary,
-                    const int32_t *class_tiles, void *plan, size_t plan_bytes);
+                    const int32_t *class_tiles, int32_t flags, void *plan, size_t plan_bytes);
 
 /* Number of launches of a plan, in total and (per_level: NULL or `levels`
- * entries) per level, index j for level j+1. */
+ * entries) per level, index j for level j+1; a head launch counts at level
+ * 1, and level 2 then has none. */
 int dwt2_batch_launches(const void *plan, size_t plan_bytes, int32_t *launches,
                         int32_t *per_level);
 

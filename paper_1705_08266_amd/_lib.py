@@ -61,6 +61,7 @@ class LevelJob(ctypes.Structure):
 _LevelJobP = ctypes.POINTER(LevelJob)
 SIZE_CLASSES = 4
 BATCH_PERSISTENT = 1      # DWT2_BATCH_PERSISTENT
+PLAN_HEAD = 1             # DWT2_PLAN_HEAD: levels 1 and 2 of a batch in one head launch
 
 SIGNATURES = {
     "dwt2_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32]),
@@ -85,9 +86,9 @@ SIGNATURES = {
     "dwt2_default_tile": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
     "dwt2_size_class": (ctypes.c_int, [_i32, _i32]),
     "dwt2_batch_plan_bytes": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32,
-                                             _ip32, ctypes.POINTER(ctypes.c_size_t)]),
+                                             _ip32, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "dwt2_batch_plan": (ctypes.c_int, [_ImageP, _i32, _i32, _i32, _i32, _i32, _i32, _ip32,
-                                       _vp, _sz]),
+                                       _i32, _vp, _sz]),
     "dwt2_batch_launches": (ctypes.c_int, [_vp, _sz, _ip32, _ip32]),
     "dwt2_batch_run": (ctypes.c_int, [_vp, _sz, _vp, _i32, _i32, _vp]),
     "dwt2_forward_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),

@@ -47,9 +47,9 @@ def _class_tiles(class_tiles):
 
 
 def make_plan(srcs, dsts, workspaces, inverse=False, wavelet="cdf97", levels=1,
-              class_tiles=None):
+              class_tiles=None, fuse_head=False):
     """The host plan of a batched transform srcs[i] -> dsts[i] (a ctypes byte
-    buffer)."""
+    buffer). fuse_head: levels 1 and 2 of every image in one head launch."""
     if not (len(srcs) == len(dsts) == len(workspaces)) or not srcs:
         raise ValueError("need one dst and one workspace per src, and at least one image")
     dt = _dtype_code(srcs[0])
@@ -61,7 +61,8 @@ def make_plan(srcs, dsts, workspaces, inverse=False, wavelet="cdf97", levels=1,
     arr = _image_array(srcs, dsts, workspaces)
     lib = load()
     args = (arr, len(srcs), dt, _wavelet(wavelet), int(levels), int(bool(inverse)),
-            _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _class_tiles(class_tiles))
+            _lib.EXT_WHOLE_SAMPLE_SYMMETRIC, _class_tiles(class_tiles),
+            _lib.PLAN_HEAD if fuse_head else 0)
     n = ctypes.c_size_t()
     _lib.check(lib.dwt2_batch_plan_bytes(*args, ctypes.byref(n)), "dwt2_batch_plan_bytes")
     buf = (ctypes.c_ubyte * n.value)()
@@ -73,19 +74,21 @@ class BatchPlan:
     """A fixed batch of images with outputs, workspaces and the plan's device
     copy allocated once; run() enqueues it, capture()/replay() use a graph."""
 
-    def __init__(self, srcs, inverse, wavelet, levels, scheme, class_tiles, persistent=False):
+    def __init__(self, srcs, inverse, wavelet, levels, scheme, class_tiles, persistent=False,
+                 fuse_head=False):
         import torch
         self.srcs = list(srcs)
         self.inverse = inverse
         self.wavelet, self.levels, self.scheme = wavelet, levels, scheme
         self.class_tiles = class_tiles
         self.persistent = persistent
+        self.fuse_head = fuse_head
         self.outputs = [torch.empty_like(s) for s in self.srcs]
         self.workspaces = [
             torch.empty(max(1, workspace_bytes(s.shape[1], s.shape[0], levels) // 4),
                         dtype=torch.float32, device=s.device) for s in self.srcs]
         self.host_plan = make_plan(self.srcs, self.outputs, self.workspaces, inverse, wavelet,
-                                   levels, class_tiles)
+                                   levels, class_tiles, fuse_head)
         host = torch.frombuffer(bytearray(self.host_plan), dtype=torch.uint8)
         self.device_plan = host.to(self.srcs[0].device)
         torch.cuda.synchronize()
@@ -93,13 +96,13 @@ class BatchPlan:
 
     @classmethod
     def forward(cls, images, levels=1, wavelet="cdf97", scheme="nonseparable", class_tiles=None,
-                persistent=False):
-        return cls(images, False, wavelet, levels, scheme, class_tiles, persistent)
+                persistent=False, fuse_head=False):
+        return cls(images, False, wavelet, levels, scheme, class_tiles, persistent, fuse_head)
 
     @classmethod
     def inverse_of(cls, coefs, levels=1, wavelet="cdf97", scheme="nonseparable",
-                   class_tiles=None, persistent=False):
-        return cls(coefs, True, wavelet, levels, scheme, class_tiles, persistent)
+                   class_tiles=None, persistent=False, fuse_head=False):
+        return cls(coefs, True, wavelet, levels, scheme, class_tiles, persistent, fuse_head)
 
     def launches(self):
         """(total launches, launches per level j = 1..L)."""

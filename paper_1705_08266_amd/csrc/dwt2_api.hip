@@ -475,7 +475,7 @@ bool batch_images_conflict(const dwt2_image *images, int n, int dtype, int level
 // each image's first tile and the images' level parameters. Offsets are from
 // the start of the plan; sections are 256-byte aligned.
 constexpr uint32_t kPlanMagic = 0x42545744u;   // "DWTB"
-constexpr int32_t kPlanVersion = 1;
+constexpr int32_t kPlanVersion = 2;
 
 struct PlanHeader {
     uint32_t magic;
@@ -484,8 +484,8 @@ struct PlanHeader {
     uint64_t bytes;
 };
 struct PlanLaunch {
-    int32_t level;          // 1-based
-    int32_t tile;           // tile configuration
+    int32_t level;          // 1-based; a head launch (levels 1 and 2) has level 1
+    int32_t tile;           // tile configuration, or DWT2_TILE_HEAD
     int32_t f32_a, f32_b;   // operand types, as indexed in the single-level tables
     int32_t images;         // images in this launch
     int32_t total;          // tiles in this launch
@@ -498,6 +498,13 @@ const PlanLaunch *plan_launches(const PlanHeader *h) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+const FwdHeadPlanTable &fwd_head_plan_table(int dt) {
+    return dt == DWT2_F32 ? kFwdHeadPlanF32 : dt == DWT2_F16 ? kFwdHeadPlanF16 : kFwdHeadPlanBF16;
+}
+const InvHeadPlanTable &inv_head_plan_table(int dt) {
+    return dt == DWT2_F32 ? kInvHeadPlanF32 : dt == DWT2_F16 ? kInvHeadPlanF16 : kInvHeadPlanBF16;
+}
 
 const FwdTableTable &fwd_plan_table(int dt) {
     return dt == DWT2_F32 ? kFwdPlanF32 : dt == DWT2_F16 ? kFwdPlanF16 : kFwdPlanBF16;
@@ -518,11 +525,15 @@ int check_plan(const void *plan, size_t bytes, const PlanHeader **out) {
     if (sizeof(PlanHeader) + (size_t)h->nlaunch * sizeof(PlanLaunch) > bytes)
         return DWT2_ERR_INVALID_ARG;
     const PlanLaunch *L = plan_launches(h);
-    const size_t psize = h->inverse ? sizeof(InvParams) : sizeof(FwdParams);
     for (int k = 0; k < h->nlaunch; ++k) {
         const PlanLaunch &l = L[k];
-        if (l.level < 1 || l.level > h->levels || l.tile < 0 || l.tile >= kNumTiles ||
-            (l.f32_a | l.f32_b) & ~1 || l.images < 1 || l.images > h->n || l.total < 1)
+        const bool head = l.tile == DWT2_TILE_HEAD;
+        const size_t psize = head ? (h->inverse ? sizeof(InvHead) : sizeof(FwdHead))
+                                  : (h->inverse ? sizeof(InvParams) : sizeof(FwdParams));
+        if (head ? (l.level != 1 || h->levels < 2) : (l.tile < 0 || l.tile >= kNumTiles))
+            return DWT2_ERR_INVALID_ARG;
+        if (l.level < 1 || l.level > h->levels || (l.f32_a | l.f32_b) & ~1 || l.images < 1 ||
+            l.images > h->n || l.total < 1)
             return DWT2_ERR_INVALID_ARG;
         if (l.off_img + 4 * (uint64_t)l.total > bytes ||
             l.off_start + 4 * (uint64_t)l.images > bytes ||
@@ -535,13 +546,17 @@ int check_plan(const void *plan, size_t bytes, const PlanHeader **out) {
 
 // Plans an L-level batched transform: for each level (forward 1..L, inverse
 // L..1) and each tile configuration its images' size classes use, one launch.
+// With DWT2_PLAN_HEAD and L >= 2, levels 1 and 2 of every image are one head
+// launch instead (planned at level 1).
 int build_plan(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavelet,
                int32_t levels, int32_t inverse, int32_t boundary, const int32_t *class_tiles,
-               std::vector<unsigned char> &out) {
+               int32_t flags, std::vector<unsigned char> &out) {
     if (n < 1 || !images) return DWT2_ERR_INVALID_ARG;
     if (!valid_dtype(dtype) || !valid_wavelet(wavelet) ||
-        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC || (inverse != 0 && inverse != 1))
+        boundary != DWT2_EXT_WHOLE_SAMPLE_SYMMETRIC || (inverse != 0 && inverse != 1) ||
+        (flags & ~DWT2_PLAN_HEAD))
         return DWT2_ERR_UNSUPPORTED;
+    const bool fuse_head = (flags & DWT2_PLAN_HEAD) && levels >= 2;
     if (levels < 1 || levels > 16) return DWT2_ERR_INVALID_ARG;
     int ctile[DWT2_SIZE_CLASSES];
     for (int c = 0; c < DWT2_SIZE_CLASSES; ++c) {
@@ -560,10 +575,79 @@ int build_plan(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavel
         std::vector<int32_t> img, start;
         std::vector<FwdParams> fp;
         std::vector<InvParams> ip;
+        std::vector<FwdHead> fh;
+        std::vector<InvHead> ih;
     };
     std::vector<Group> groups;
+    // one head launch over every image: levels 1 and 2, as dwt2_forward /
+    // dwt2_inverse plan them (the level-2 low-low band in the workspace unless
+    // it is the last level's)
+    auto add_head = [&]() -> int {
+        Group G;
+        G.l = PlanLaunch{};
+        G.l.level = 1;
+        G.l.tile = DWT2_TILE_HEAD;
+        const int ll2_f32 = levels > 2 || dtype == DWT2_F32;
+        G.l.f32_a = inverse ? ll2_f32 : dtype == DWT2_F32;
+        G.l.f32_b = inverse ? dtype == DWT2_F32 : ll2_f32;
+        for (int i = 0; i < n; ++i) {
+            const dwt2_image &im = images[i];
+            const int W = im.width, H = im.height;
+            float *ws0 = static_cast<float *>(im.workspace);
+            float *ws1 = ws0 + (size_t)(W / 2) * (H / 2);
+            int tiles;
+            if (inverse) {
+                const char *cb = static_cast<const char *>(im.src);
+                const int64_t cp = im.src_pitch;
+                InvHead hd;
+                hd.l2 = inv_params(levels == 2 ? im.src : (const void *)ws1,
+                                   levels == 2 ? cp : W / 4, levels == 2 ? dtype : DWT2_F32,
+                                   cb + (size_t)(W / 4) * es, cb + (size_t)((int64_t)(H / 4) * cp) * es,
+                                   cb + (size_t)((int64_t)(H / 4) * cp + W / 4) * es, cp, dtype,
+                                   ws0, W / 2, DWT2_F32, W / 2, H / 2, wavelet, 0);
+                hd.l1 = inv_params(ws0, W / 2, DWT2_F32, cb + (size_t)(W / 2) * es,
+                                   cb + (size_t)((int64_t)(H / 2) * cp) * es,
+                                   cb + (size_t)((int64_t)(H / 2) * cp + W / 2) * es, cp, dtype,
+                                   im.dst, im.dst_pitch, dtype, W, H, wavelet, 0);
+                hd.tiles_x = (hd.l1.nqx + FwdHeadGeom::IOX1 - 1) / FwdHeadGeom::IOX1;
+                hd.tiles_y = (hd.l1.nqy + FwdHeadGeom::IOY1 - 1) / FwdHeadGeom::IOY1;
+                tiles = hd.tiles_x * hd.tiles_y;
+                G.ih.push_back(hd);
+            } else {
+                char *cb = static_cast<char *>(im.dst);
+                const int64_t cp = im.dst_pitch;
+                FwdHead hd;
+                hd.l1 = fwd_params(im.src, im.src_pitch, dtype, W, H, ws0, W / 2, DWT2_F32,
+                                   cb + (size_t)(W / 2) * es, cb + (size_t)((int64_t)(H / 2) * cp) * es,
+                                   cb + (size_t)((int64_t)(H / 2) * cp + W / 2) * es, cp, dtype,
+                                   wavelet, 0);
+                hd.l2 = fwd_params(ws0, W / 2, DWT2_F32, W / 2, H / 2,
+                                   levels == 2 ? im.dst : (void *)ws1, levels == 2 ? cp : W / 4,
+                                   levels == 2 ? dtype : DWT2_F32, cb + (size_t)(W / 4) * es,
+                                   cb + (size_t)((int64_t)(H / 4) * cp) * es,
+                                   cb + (size_t)((int64_t)(H / 4) * cp + W / 4) * es, cp, dtype,
+                                   wavelet, 0);
+                hd.tiles_x = (hd.l2.nqx + FwdHeadGeom::FOX2 - 1) / FwdHeadGeom::FOX2;
+                hd.tiles_y = (hd.l2.nqy + FwdHeadGeom::FOY2 - 1) / FwdHeadGeom::FOY2;
+                tiles = hd.tiles_x * hd.tiles_y;
+                G.fh.push_back(hd);
+            }
+            G.start.push_back((int32_t)G.img.size());
+            if ((int64_t)G.img.size() + tiles > (int64_t)INT32_MAX) return DWT2_ERR_INVALID_ARG;
+            G.img.insert(G.img.end(), (size_t)tiles, (int32_t)i);
+        }
+        groups.push_back(std::move(G));
+        return DWT2_OK;
+    };
     for (int step = 0; step < levels; ++step) {
         const int j = inverse ? levels - step : step + 1;
+        if (fuse_head && j <= 2) {   // the head launch, planned once at level 2 (inverse) or 1
+            if (j == (inverse ? 2 : 1)) {
+                const int st = add_head();
+                if (st) return st;
+            }
+            continue;
+        }
         const int first = (int)groups.size();
         for (int i = 0; i < n; ++i) {
             const dwt2_image &im = images[i];
@@ -632,8 +716,8 @@ int build_plan(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavel
         G.l.off_start = off;
         off = align256(off + 4 * G.start.size());
         G.l.off_params = off;
-        off = align256(off + (inverse ? sizeof(InvParams) * G.ip.size()
-                                      : sizeof(FwdParams) * G.fp.size()));
+        off = align256(off + sizeof(InvParams) * G.ip.size() + sizeof(FwdParams) * G.fp.size() +
+                       sizeof(InvHead) * G.ih.size() + sizeof(FwdHead) * G.fh.size());
     }
     out.assign(off, 0);
     PlanHeader h{kPlanMagic, kPlanVersion, n, levels, inverse, dtype, wavelet,
@@ -645,10 +729,11 @@ int build_plan(const dwt2_image *images, int32_t n, int32_t dtype, int32_t wavel
                     sizeof(PlanLaunch));
         std::memcpy(out.data() + G.l.off_img, G.img.data(), 4 * G.img.size());
         std::memcpy(out.data() + G.l.off_start, G.start.data(), 4 * G.start.size());
-        if (inverse)
-            std::memcpy(out.data() + G.l.off_params, G.ip.data(), sizeof(InvParams) * G.ip.size());
-        else
-            std::memcpy(out.data() + G.l.off_params, G.fp.data(), sizeof(FwdParams) * G.fp.size());
+        unsigned char *prm = out.data() + G.l.off_params;
+        if (!G.ih.empty()) std::memcpy(prm, G.ih.data(), sizeof(InvHead) * G.ih.size());
+        if (!G.fh.empty()) std::memcpy(prm, G.fh.data(), sizeof(FwdHead) * G.fh.size());
+        if (!G.ip.empty()) std::memcpy(prm, G.ip.data(), sizeof(InvParams) * G.ip.size());
+        if (!G.fp.empty()) std::memcpy(prm, G.fp.data(), sizeof(FwdParams) * G.fp.size());
     }
     return DWT2_OK;
 }
@@ -990,11 +1075,12 @@ int dwt2_size_class(int32_t width, int32_t height) {
 
 int dwt2_batch_plan_bytes(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
                           dwt2_wavelet wavelet, int32_t levels, int32_t inverse,
-                          dwt2_boundary boundary, const int32_t *class_tiles, size_t *bytes) {
+                          dwt2_boundary boundary, const int32_t *class_tiles, int32_t flags,
+                          size_t *bytes) {
     if (!bytes) return DWT2_ERR_INVALID_ARG;
     std::vector<unsigned char> plan;
     const int st = build_plan(images, n, dtype, wavelet, levels, inverse, boundary, class_tiles,
-                              plan);
+                              flags, plan);
     if (st) return st;
     *bytes = plan.size();
     return DWT2_OK;
@@ -1002,10 +1088,11 @@ int dwt2_batch_plan_bytes(const dwt2_image *images, int32_t n, dwt2_dtype dtype,
 
 int dwt2_batch_plan(const dwt2_image *images, int32_t n, dwt2_dtype dtype, dwt2_wavelet wavelet,
                     int32_t levels, int32_t inverse, dwt2_boundary boundary,
-                    const int32_t *class_tiles, void *plan, size_t plan_bytes) {
+                    const int32_t *class_tiles, int32_t flags, void *plan, size_t plan_bytes) {
     if (!plan) return DWT2_ERR_INVALID_ARG;
     std::vector<unsigned char> v;
-    const int st = build_plan(images, n, dtype, wavelet, levels, inverse, boundary, class_tiles, v);
+    const int st = build_plan(images, n, dtype, wavelet, levels, inverse, boundary, class_tiles,
+                              flags, v);
     if (st) return st;
     if (plan_bytes < v.size()) return DWT2_ERR_WORKSPACE;
     std::memcpy(plan, v.data(), v.size());
@@ -1040,7 +1127,21 @@ int dwt2_batch_run(const void *plan, size_t plan_bytes, const void *plan_device,
     for (int k = 0; k < h->nlaunch; ++k) {
         const PlanLaunch &l = L[k];
         hipError_t e;
-        if (h->inverse) {
+        if (l.tile == DWT2_TILE_HEAD && h->inverse) {
+            TableLaunch<InvHead> tl{reinterpret_cast<const int32_t *>(dev + l.off_img),
+                                    reinterpret_cast<const int32_t *>(dev + l.off_start),
+                                    reinterpret_cast<const InvHead *>(dev + l.off_params),
+                                    l.total};
+            e = inv_head_plan_table(h->dtype)[h->wavelet][scheme][l.f32_a][l.f32_b](
+                tl, persistent, stream);
+        } else if (l.tile == DWT2_TILE_HEAD) {
+            TableLaunch<FwdHead> tl{reinterpret_cast<const int32_t *>(dev + l.off_img),
+                                    reinterpret_cast<const int32_t *>(dev + l.off_start),
+                                    reinterpret_cast<const FwdHead *>(dev + l.off_params),
+                                    l.total};
+            e = fwd_head_plan_table(h->dtype)[h->wavelet][scheme][l.f32_a][l.f32_b](
+                tl, persistent, stream);
+        } else if (h->inverse) {
             TableLaunch<InvParams> tl{reinterpret_cast<const int32_t *>(dev + l.off_img),
                                       reinterpret_cast<const int32_t *>(dev + l.off_start),
                                       reinterpret_cast<const InvParams *>(dev + l.off_params),

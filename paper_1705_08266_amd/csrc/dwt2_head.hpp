@@ -81,21 +81,40 @@ constexpr int kFwdHeadWavesPerSimd =
     (SCH == SEP && sizeof(TIN) == 2) ? (2 * WAVES + 3) / 4 : (WAVES + 3) / 4;
 template <int WAVES>
 constexpr int kInvHeadWavesPerSimd = (WAVES + 3) / 4;
+// The batched heads (which read their parameters from the plan, one more
+// register or so) are all held to the two-workgroup budget.
+template <int WAVES>
+constexpr int kTableHeadWavesPerSimd = (2 * WAVES + 3) / 4;
 
+// LDS of a head workgroup: the mailbox serves the finer level's exchanges, then
+// the coarser level's (smaller); ll1 holds the level j low-low band as the four
+// components of the level j+1 quads, [phase][row][column].
+template <int WAVES, int H2>
+struct HeadLds {
+    Mailbox<2, WAVES> box;
+    float ll1[4][H2][64];
+};
+
+template <int ROWS, int WAVES>
+using FwdHeadLds = HeadLds<WAVES, HeadGeom<ROWS, WAVES>::FH2>;
+template <int ROWS, int WAVES>
+using InvHeadLds = HeadLds<WAVES, HeadGeom<ROWS, WAVES>::IH2>;
+
+// Levels j and j+1 of forward head tile t (row-major over tiles_x x tiles_y).
+// Wavefronts below the coarser level's window return early, after passing its
+// barriers.
 template <int WV, int SCH, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
-__global__ __launch_bounds__(64 * WAVES, (kFwdHeadWavesPerSimd<SCH, WAVES, TIN>)) void fwd_head_kernel(
-    FwdHead hd) {
+__device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
+                                              FwdHeadLds<ROWS, WAVES> &lds) {
     using G = HeadGeom<ROWS, WAVES>;
     using L = Wavelet<WV>;
     constexpr int RG = G::RG, H2 = G::FH2, R2 = G::FROWS2, NR1 = G::NR1;
-    __shared__ Mailbox<2, WAVES> box;     // level j exchanges, then level j+1's (smaller)
-    __shared__ float ll1[4][H2][64];      // level j low-low, as the four components of
-                                          // the level j+1 quads: [phase][row][column]
+    Mailbox<2, WAVES> &box = lds.box;
+    float(&ll1)[4][H2][64] = lds.ll1;
     const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
     const float sHH = (float)(L::ZH * L::ZH);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = block_tile();
     const int ty = t / hd.tiles_x, tx = t - ty * hd.tiles_x;
     const int ox2 = tx * G::FOX2, oy2 = ty * G::FOY2;   // owned block of level j+1
 
@@ -196,18 +215,19 @@ __global__ __launch_bounds__(64 * WAVES, (kFwdHeadWavesPerSimd<SCH, WAVES, TIN>)
     }
 }
 
+// Levels j+1 and j of inverse head tile t (row-major over tiles_x x tiles_y).
 template <int WV, int SCH, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
-__global__ __launch_bounds__(64 * WAVES, kInvHeadWavesPerSimd<WAVES>) void inv_head_kernel(InvHead hd) {
+__device__ __forceinline__ void inv_head_tile(const InvHead &hd, const int t,
+                                              InvHeadLds<ROWS, WAVES> &lds) {
     using G = HeadGeom<ROWS, WAVES>;
     using L = Wavelet<WV>;
     constexpr int RG = G::RG, H2 = G::IH2, R2 = G::IROWS2, NR1 = G::NR1;
-    __shared__ Mailbox<2, WAVES> box;     // level j+1 exchanges (smaller), then level j's
-    __shared__ float ll1[4][H2][64];      // level j low-low as level j+1 output quads
+    Mailbox<2, WAVES> &box = lds.box;     // level j+1 exchanges (smaller), then level j's
+    float(&ll1)[4][H2][64] = lds.ll1;     // level j low-low as level j+1 output quads
     const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
     const float uHH = (float)(1.0 / (L::ZH * L::ZH));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = block_tile();
     const int ty = t / hd.tiles_x, tx = t - ty * hd.tiles_x;
     const int ox1 = tx * G::IOX1, oy1 = ty * G::IOY1;    // owned block of level j
     const int wx1 = ox1 - 2, wy1 = oy1 - RG;             // level j window origin (even)
@@ -307,6 +327,49 @@ __global__ __launch_bounds__(64 * WAVES, kInvHeadWavesPerSimd<WAVES>) void inv_h
                 }
             }
         }
+    }
+}
+
+// One workgroup per tile of one image.
+template <int WV, int SCH, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES, (kFwdHeadWavesPerSimd<SCH, WAVES, TIN>)) void fwd_head_kernel(
+    FwdHead hd) {
+    __shared__ FwdHeadLds<ROWS, WAVES> lds;
+    fwd_head_tile<WV, SCH, ROWS, WAVES, TIN, TLL, TB>(hd, block_tile(), lds);
+}
+
+template <int WV, int SCH, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES, kInvHeadWavesPerSimd<WAVES>) void inv_head_kernel(InvHead hd) {
+    __shared__ InvHeadLds<ROWS, WAVES> lds;
+    inv_head_tile<WV, SCH, ROWS, WAVES, TLL, TB, TOUT>(hd, block_tile(), lds);
+}
+
+// Heads of a planned batch: the tiles of every image in one launch, each
+// image's parameters in the device copy of the plan. A workgroup walks the
+// tiles t = its id, id + gridDim.x, ... below `total` (several when the grid is
+// capped at the resident workgroups), with a barrier between tiles, which
+// share the LDS.
+template <int WV, int SCH, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES, kTableHeadWavesPerSimd<WAVES>) void fwd_head_table_kernel(
+    TableLaunch<FwdHead> tl) {
+    __shared__ FwdHeadLds<ROWS, WAVES> lds;
+    for (int t = block_tile(); t < tl.total; t += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(tl.img[t]);
+        const FwdHead hd = tl.params[i];
+        fwd_head_tile<WV, SCH, ROWS, WAVES, TIN, TLL, TB>(hd, t - tl.start[i], lds);
+        __syncthreads();
+    }
+}
+
+template <int WV, int SCH, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES, kTableHeadWavesPerSimd<WAVES>) void inv_head_table_kernel(
+    TableLaunch<InvHead> tl) {
+    __shared__ InvHeadLds<ROWS, WAVES> lds;
+    for (int t = block_tile(); t < tl.total; t += gridDim.x) {
+        const int i = __builtin_amdgcn_readfirstlane(tl.img[t]);
+        const InvHead hd = tl.params[i];
+        inv_head_tile<WV, SCH, ROWS, WAVES, TLL, TB, TOUT>(hd, t - tl.start[i], lds);
+        __syncthreads();
     }
 }
 

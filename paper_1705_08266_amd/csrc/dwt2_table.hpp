@@ -314,6 +314,63 @@ constexpr InvHeadTable make_inv_head_table() {
              {inv_head_types<T, CDF53, NONSEP>(), inv_head_types<T, CDF53, SEP>()}}};
 }
 
+// Heads of a planned batch: one launch over the head tiles of every image,
+// indexed as the single-image head tables. `persistent` caps the grid at the
+// workgroups that fit on the device at once.
+using FwdHeadTableLauncher = hipError_t (*)(const TableLaunch<FwdHead> &, bool, hipStream_t);
+using InvHeadTableLauncher = hipError_t (*)(const TableLaunch<InvHead> &, bool, hipStream_t);
+
+template <int WV, int SCH, typename TIN, typename TLL, typename T>
+hipError_t launch_fwd_head_table(const TableLaunch<FwdHead> &tl, bool persistent, hipStream_t s) {
+    const auto k = fwd_head_table_kernel<WV, SCH, kHeadRows, kHeadWaves, TIN, TLL, T>;
+    int grid = tl.total;
+    if (persistent) {
+        static const int resident = resident_blocks((const void *)k, 64 * kHeadWaves);
+        grid = grid < resident ? grid : resident;
+    }
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kHeadWaves), 0, s, tl);
+    return hipGetLastError();
+}
+template <int WV, int SCH, typename TLL, typename T, typename TOUT>
+hipError_t launch_inv_head_table(const TableLaunch<InvHead> &tl, bool persistent, hipStream_t s) {
+    const auto k = inv_head_table_kernel<WV, SCH, kHeadRows, kHeadWaves, TLL, T, TOUT>;
+    int grid = tl.total;
+    if (persistent) {
+        static const int resident = resident_blocks((const void *)k, 64 * kHeadWaves);
+        grid = grid < resident ? grid : resident;
+    }
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kHeadWaves), 0, s, tl);
+    return hipGetLastError();
+}
+
+using FwdHeadPlanTable = std::array<std::array<std::array<std::array<FwdHeadTableLauncher, 2>, 2>, 2>, 2>;
+using InvHeadPlanTable = std::array<std::array<std::array<std::array<InvHeadTableLauncher, 2>, 2>, 2>, 2>;
+
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<FwdHeadTableLauncher, 2>, 2> fwd_head_plan_types() {
+    return {{{&launch_fwd_head_table<WV, SCH, T, T, T>, &launch_fwd_head_table<WV, SCH, T, float, T>},
+             {&launch_fwd_head_table<WV, SCH, float, T, T>,
+              &launch_fwd_head_table<WV, SCH, float, float, T>}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<InvHeadTableLauncher, 2>, 2> inv_head_plan_types() {
+    return {{{&launch_inv_head_table<WV, SCH, T, T, T>, &launch_inv_head_table<WV, SCH, T, T, float>},
+             {&launch_inv_head_table<WV, SCH, float, T, T>,
+              &launch_inv_head_table<WV, SCH, float, T, float>}}};
+}
+template <typename T>
+constexpr FwdHeadPlanTable make_fwd_head_plan_table() {
+    return {{{fwd_head_plan_types<T, CDF97, NONSEP>(), fwd_head_plan_types<T, CDF97, SEP>()},
+             {fwd_head_plan_types<T, CDF53, NONSEP>(), fwd_head_plan_types<T, CDF53, SEP>()}}};
+}
+template <typename T>
+constexpr InvHeadPlanTable make_inv_head_plan_table() {
+    return {{{inv_head_plan_types<T, CDF97, NONSEP>(), inv_head_plan_types<T, CDF97, SEP>()},
+             {inv_head_plan_types<T, CDF53, NONSEP>(), inv_head_plan_types<T, CDF53, SEP>()}}};
+}
+
 // The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels only, index [wavelet][scheme - NONSEP_LDS][config].
 using FwdLdsTable = std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>;
 using InvLdsTable = std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>;
@@ -355,6 +412,8 @@ extern InvTableTable kInvPlanF32, kInvPlanF16, kInvPlanBF16;
 extern FwdTailTable kFwdTailF32, kFwdTailF16, kFwdTailBF16;
 extern FwdHeadTable kFwdHeadF32, kFwdHeadF16, kFwdHeadBF16;
 extern InvHeadTable kInvHeadF32, kInvHeadF16, kInvHeadBF16;
+extern FwdHeadPlanTable kFwdHeadPlanF32, kFwdHeadPlanF16, kFwdHeadPlanBF16;
+extern InvHeadPlanTable kInvHeadPlanF32, kInvHeadPlanF16, kInvHeadPlanBF16;
 extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
 extern FwdLdsTable kFwdLds;
 extern InvLdsTable kInvLds;

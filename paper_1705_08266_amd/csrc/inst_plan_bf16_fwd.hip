@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdTableTable kFwdPlanBF16 = make_fwd_table_table<bf16_t>();
+FwdHeadPlanTable kFwdHeadPlanBF16 = make_fwd_head_plan_table<bf16_t>();
 }  // namespace dwt2

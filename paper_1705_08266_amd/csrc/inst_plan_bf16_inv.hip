@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvTableTable kInvPlanBF16 = make_inv_table_table<bf16_t>();
+InvHeadPlanTable kInvHeadPlanBF16 = make_inv_head_plan_table<bf16_t>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdTableTable kFwdPlanF16 = make_fwd_table_table<__half>();
+FwdHeadPlanTable kFwdHeadPlanF16 = make_fwd_head_plan_table<__half>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvTableTable kInvPlanF16 = make_inv_table_table<__half>();
+InvHeadPlanTable kInvHeadPlanF16 = make_inv_head_plan_table<__half>();
 }  // namespace dwt2

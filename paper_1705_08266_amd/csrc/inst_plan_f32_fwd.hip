@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdTableTable kFwdPlanF32 = make_fwd_table_table<float>();
+FwdHeadPlanTable kFwdHeadPlanF32 = make_fwd_head_plan_table<float>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvTableTable kInvPlanF32 = make_inv_table_table<float>();
+InvHeadPlanTable kInvHeadPlanF32 = make_inv_head_plan_table<float>();
 }  // namespace dwt2

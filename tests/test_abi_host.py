@@ -196,9 +196,9 @@ def test_exchange_ablation_scheme_limits():
         lib = _lib.load()
         img = (_lib.Image * 1)(_lib.Image(FAKE, 64, FAKE + (1 << 24), 64, None, 0, 64, 64))
         n = ctypes.c_size_t()
-        assert lib.dwt2_batch_plan_bytes(img, 1, 0, 0, 1, 0, 0, None, ctypes.byref(n)) == 0
+        assert lib.dwt2_batch_plan_bytes(img, 1, 0, 0, 1, 0, 0, None, 0, ctypes.byref(n)) == 0
         plan = (ctypes.c_ubyte * n.value)()
-        assert lib.dwt2_batch_plan(img, 1, 0, 0, 1, 0, 0, None, plan, n.value) == 0
+        assert lib.dwt2_batch_plan(img, 1, 0, 0, 1, 0, 0, None, 0, plan, n.value) == 0
         assert lib.dwt2_batch_run(plan, n.value, FAKE, sch, 0, None) == U
         assert lib.dwt2_forward_level_batch(None, 0, 0, sch, None, None) == U
     assert _fwd(scheme=4) == U

@@ -32,16 +32,18 @@ def _images(sizes, levels):
     return arr
 
 
-def _plan(sizes, levels, inverse=0, class_tiles=None):
+def _plan(sizes, levels, inverse=0, class_tiles=None, flags=0):
     lib = _lib.load()
     imgs = _images(sizes, levels)
     ct = None if class_tiles is None else (ctypes.c_int32 * 4)(*class_tiles)
     n = ctypes.c_size_t()
-    st = lib.dwt2_batch_plan_bytes(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, ctypes.byref(n))
+    st = lib.dwt2_batch_plan_bytes(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, flags,
+                                   ctypes.byref(n))
     assert st == 0, st
     buf = (ctypes.c_ubyte * n.value)()
-    assert lib.dwt2_batch_plan(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, buf, n.value) == 0
-    assert lib.dwt2_batch_plan(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, buf,
+    assert lib.dwt2_batch_plan(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, flags, buf,
+                               n.value) == 0
+    assert lib.dwt2_batch_plan(imgs, len(sizes), 0, 0, levels, inverse, 0, ct, flags, buf,
                                n.value - 1) == _lib.ERR_WORKSPACE
     return bytes(buf)
 
@@ -122,15 +124,15 @@ def test_plan_rejects_bad_batches():
     lib = _lib.load()
     n = ctypes.c_size_t()
     imgs = _images([(64, 64)], 1)
-    assert lib.dwt2_batch_plan_bytes(imgs, 0, 0, 0, 1, 0, 0, None, ctypes.byref(n)) == \
+    assert lib.dwt2_batch_plan_bytes(imgs, 0, 0, 0, 1, 0, 0, None, 0, ctypes.byref(n)) == \
         _lib.ERR_INVALID_ARG                                                   # no images
-    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 1, 2, 0, None, ctypes.byref(n)) == \
+    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 1, 2, 0, None, 0, ctypes.byref(n)) == \
         _lib.ERR_UNSUPPORTED                                                   # direction
     ct = (ctypes.c_int32 * 4)(0, 0, 0, 17)
-    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 1, 0, 0, ct, ctypes.byref(n)) == \
+    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 1, 0, 0, ct, 0, ctypes.byref(n)) == \
         _lib.ERR_UNSUPPORTED                                                   # tile id
     imgs = _images([(64, 64)], 1)
-    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 7, 0, 0, None, ctypes.byref(n)) == \
+    assert lib.dwt2_batch_plan_bytes(imgs, 1, 0, 0, 7, 0, 0, None, 0, ctypes.byref(n)) == \
         _lib.ERR_INVALID_ARG                                                   # 64 % 128
 
 
@@ -171,3 +173,58 @@ def test_tune_default_candidates_are_the_compiled_configurations():
     seen = set()
     autotune.tune(timer=lambda c, t: seen.add(t) or float(t), device_name="dev")
     assert seen == {c[0] for c in dwt.tile_configs("cdf97")}
+
+
+# Head tile grids of the 12-wavefront, 4-row head: a forward tile owns 58 x 18
+# level-2 quads, an inverse tile 116 x 44 level-1 quads.
+def _head_tiles(w, h, inverse):
+    if inverse:
+        return (-(-(w // 2) // 116)) * (-(-(h // 2) // 44))
+    return (-(-(w // 4) // 58)) * (-(-(h // 4) // 18))
+
+
+@pytest.mark.parametrize("inverse", [0, 1])
+def test_head_plan_fuses_levels_one_and_two(inverse):
+    sizes = [(64, 96), (256, 128), (1024, 512), (96, 64), (4096, 128), (512, 512), (32, 32)]
+    L = 3
+    plan = _plan(sizes, L, inverse, flags=_lib.PLAN_HEAD)
+    h, launches = _parse(plan)
+    assert h["nlaunch"] == L - 1
+    assert [l[0] for l in launches] == ([3, 1] if inverse else [1, 3])
+    head = [l for l in launches if l[1] == _lib.TILE_HEAD]
+    assert len(head) == 1
+    level, tile, fa, fb, images, total, off_img, off_start, off_params = head[0]
+    assert level == 1 and images == len(sizes) and (fa, fb) == (1, 1)
+    img = struct.unpack_from(f"<{total}i", plan, off_img)
+    start = struct.unpack_from(f"<{images}i", plan, off_start)
+    expect = [_head_tiles(w, hh, inverse) for w, hh in sizes]
+    assert total == sum(expect)
+    pos = 0
+    for i, cnt in enumerate(expect):
+        assert start[i] == pos and img[pos:pos + cnt] == (i,) * cnt
+        pos += cnt
+    lib = _lib.load()
+    n = ctypes.c_int32()
+    per = (ctypes.c_int32 * L)()
+    assert lib.dwt2_batch_launches(plan, len(plan), ctypes.byref(n), per) == 0
+    assert n.value == L - 1 and list(per) == [1, 0, 1]
+
+
+def test_head_flag_changes_nothing_with_one_level_and_unknown_flags_are_refused():
+    sizes = [(64, 64), (256, 128)]
+    assert _plan(sizes, 1, flags=_lib.PLAN_HEAD) == _plan(sizes, 1)
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    assert lib.dwt2_batch_plan_bytes(_images(sizes, 2), 2, 0, 0, 2, 0, 0, None, 2,
+                                     ctypes.byref(n)) == _lib.ERR_UNSUPPORTED
+
+
+def test_run_refuses_a_head_launch_off_level_one():
+    lib = _lib.load()
+    plan = bytearray(_plan([(64, 64), (128, 64)], 2, flags=_lib.PLAN_HEAD))
+    h, launches = _parse(bytes(plan))
+    assert [l[1] for l in launches] == [_lib.TILE_HEAD]
+    bad = bytearray(plan)
+    LAUNCH.pack_into(bad, HEADER.size, 2, *launches[0][1:])                    # level 2
+    assert lib.dwt2_batch_run((ctypes.c_ubyte * len(bad)).from_buffer(bad), len(bad), FAKE, 0,
+                              0, None) == _lib.ERR_INVALID_ARG

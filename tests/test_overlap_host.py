@@ -98,7 +98,7 @@ def _image(src, dst, ws=None, wsb=0, w=64, h=64):
 def _plan_status(imgs, levels=1, inverse=0):
     lib = _lib.load()
     n = ctypes.c_size_t()
-    return lib.dwt2_batch_plan_bytes(imgs, len(imgs), 0, 0, levels, inverse, 0, None,
+    return lib.dwt2_batch_plan_bytes(imgs, len(imgs), 0, 0, levels, inverse, 0, None, 0,
                                      ctypes.byref(n))
 
 
