@@ -668,12 +668,14 @@ SERVE_SMALL_BUDGET = 4 << 30   # a budget small enough that admission queues
 SERVE_ITERATION_MPX = 1024     # per-iteration cap on level-input pixels (Mpx; 0: none)
 
 
-def serve_workload_text(n, dtype, cap_mpx=SERVE_ITERATION_MPX):
+def serve_workload_text(n, dtype, cap_mpx=SERVE_ITERATION_MPX, heads=True):
     return (f"{n} requests drawn from {SERVE_POOL} resident inputs, square sides log-uniform "
             f"in [256, 8192] (multiples of 64), levels 1..6, forward/inverse 50/50, {dtype} "
             f"storage with FP32 intermediates, Poisson arrivals, {SERVE_BUDGET >> 30} GiB "
             f"admission budget" + (f", at most {cap_mpx:g} Mpx of level input per iteration"
-                                   if cap_mpx else ""))
+                                   if cap_mpx else "")
+            + (", two levels per step in fused head launches" if heads else
+               ", one level per step"))
 
 
 def run_serve_workload(args):
@@ -687,7 +689,8 @@ def run_serve_workload(args):
         value=sat["gpixel_per_s"], unit="Gpixel/s", n_gpus=1, steps=n, warmup=n,
         ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype=args.dtype, data="synthetic",
-        config=dict(workload=serve_workload_text(n, args.dtype, args.serve_cap), requests=n,
+        config=dict(workload=serve_workload_text(n, args.dtype, args.serve_cap,
+                                                 args.serve_heads == "on"), requests=n,
                     pixels=px,
                     iteration_cap_mpx=args.serve_cap or None),
         saturation=sat, latency_sweep=sweep, small_budget=small)), flush=True)
@@ -725,7 +728,8 @@ def serve_measure(args, n, dtype, fractions):
         rs = reqs if sub is None else reqs[:sub]
         cap = getattr(args, "serve_cap", SERVE_ITERATION_MPX)
         srv = sv.Server(budget_bytes=budget, wavelet=args.wavelet, scheme=args.scheme,
-                        dtype=dtype, max_iteration_pixels=int(cap * 1e6) if cap else None)
+                        dtype=dtype, max_iteration_pixels=int(cap * 1e6) if cap else None,
+                        fuse_heads=getattr(args, "serve_heads", "on") == "on")
         if rate is None:
             res = srv.run(rs, inputs, realtime=False)
         else:
@@ -789,6 +793,8 @@ def main():
                     help="requests in the serve workload")
     ap.add_argument("--serve-cap", type=float, default=SERVE_ITERATION_MPX,
                     help="serving: per-iteration cap on level-input pixels, Mpx (0: none)")
+    ap.add_argument("--serve-heads", default="on", choices=["on", "off"],
+                    help="serving: two levels per step in fused head launches (on) or one")
     ap.add_argument("--fuse", default="auto", choices=["auto", "off"],
                     help="auto: the library fuses the coarse levels; off: one launch per level")
     ap.add_argument("--workload", default="image", choices=["image", "batch", "serve"],
@@ -970,7 +976,7 @@ def main():
         n, px, sat, sweep, small = serve_measure(args, SERVE_REQUESTS, "f16", (0.5, 0.8, 0.95))
         at = sweep["0.8"]
         result["serving"] = dict(
-            workload=serve_workload_text(n, "f16"),
+            workload=serve_workload_text(n, "f16", heads=args.serve_heads == "on"),
             saturation_gpixel_per_s=sat["gpixel_per_s"],
             saturation_requests_per_s=sat["requests_per_s"],
             offered_per_s=at["offered_per_s"], gpixel_per_s=at["gpixel_per_s"],

@@ -359,6 +359,25 @@ int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n,
                              dwt2_wavelet wavelet, dwt2_scheme scheme,
                              const int32_t *class_tiles, hipStream_t stream);
 
+/* Two consecutive levels j and j+1 of many independent images in few
+ * launches of the fused head (levels fused as Sec. 5 suggests; the same
+ * arithmetic as two level jobs, bit for bit): n pairs, jobs[2i] the finer
+ * level j and jobs[2i+1] the coarser level j+1 of pair i, each a level job as
+ * above. The forward reads jobs[2i].full and writes both levels' bands and
+ * jobs[2i+1].ll; the inverse reads jobs[2i+1].ll and both levels' bands and
+ * writes jobs[2i].full. The band between the two levels stays on chip in
+ * FP32 and is not accessed: jobs[2i].ll and jobs[2i+1].full must be the same
+ * FP32 buffer (equal pointer and pitch), jobs[2i+1] must be half the size of
+ * jobs[2i] in each dimension, and both levels share one band storage type;
+ * else DWT2_ERR_INVALID_ARG. Pairs are grouped by storage types into launches
+ * of up to 18. Every job is checked as by the level batches, and no pair may
+ * write a buffer another pair (or the pair's other level) reads or writes.
+ * Returns a dwt2_status; nothing is enqueued on an argument error. */
+int dwt2_forward_head_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                            dwt2_scheme scheme, hipStream_t stream);
+int dwt2_inverse_head_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                            dwt2_scheme scheme, hipStream_t stream);
+
 /* Human-readable text of a status code (static storage). */
 const char *dwt2_status_string(int status);
 

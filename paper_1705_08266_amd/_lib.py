@@ -93,6 +93,8 @@ SIGNATURES = {
     "dwt2_batch_run": (ctypes.c_int, [_vp, _sz, _vp, _i32, _i32, _vp]),
     "dwt2_forward_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
     "dwt2_inverse_level_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _ip32, _vp]),
+    "dwt2_forward_head_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _vp]),
+    "dwt2_inverse_head_batch": (ctypes.c_int, [_LevelJobP, _i32, _i32, _i32, _vp]),
     "dwt2_fused_levels": (ctypes.c_int, [_i32, _i32, _i32]),
     "dwt2_head_levels": (ctypes.c_int, [_i32, _i32, _i32]),
     "dwt2_status_string": (ctypes.c_char_p, [ctypes.c_int]),

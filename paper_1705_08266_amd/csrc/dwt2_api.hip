@@ -1254,6 +1254,129 @@ int level_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t 
     return st;
 }
 
+// Head level batches: jobs[2i] is the finer level j and jobs[2i+1] the
+// coarser level j+1 of pair i, each a level job as in the level batches. The
+// band between them (the finer job's ll, the coarser job's full) stays in LDS
+// in FP32 and is not accessed, so it must be that one FP32 buffer.
+struct HeadKey {
+    int band_dt, a_f32, b_f32;
+    bool operator==(const HeadKey &o) const {
+        return band_dt == o.band_dt && a_f32 == o.a_f32 && b_f32 == o.b_f32;
+    }
+};
+
+const FwdHeadBatchTable &fwd_head_batch_table(int dt) {
+    return dt == DWT2_F32 ? kFwdHeadBatchF32 : dt == DWT2_F16 ? kFwdHeadBatchF16 : kFwdHeadBatchBF16;
+}
+const InvHeadBatchTable &inv_head_batch_table(int dt) {
+    return dt == DWT2_F32 ? kInvHeadBatchF32 : dt == DWT2_F16 ? kInvHeadBatchF16 : kInvHeadBatchBF16;
+}
+
+template <bool INV>
+int head_batch(const dwt2_level_job *jobs, int32_t n, int32_t wavelet, int32_t scheme,
+               hipStream_t stream) {
+    if (n < 0 || (n > 0 && !jobs)) return DWT2_ERR_INVALID_ARG;
+    if (!valid_wavelet(wavelet) || !valid_scheme(scheme) || lds_scheme(scheme))
+        return DWT2_ERR_UNSUPPORTED;
+    for (int i = 0; i < 2 * n; ++i) {
+        const dwt2_level_job &j = jobs[i];
+        const int st = check_level_args(j.full, j.full_pitch, j.full_dtype, j.width, j.height,
+                                        j.ll, j.ll_pitch, j.ll_dtype, j.hl, j.lh, j.hh,
+                                        j.band_pitch, j.band_dtype, wavelet, scheme, 0);
+        if (st) return st;
+    }
+    for (int i = 0; i < n; ++i) {
+        const dwt2_level_job &f = jobs[2 * i], &c = jobs[2 * i + 1];
+        if (c.width != f.width / 2 || c.height != f.height / 2 || f.ll != c.full ||
+            f.ll_pitch != c.full_pitch || f.ll_dtype != DWT2_F32 || c.full_dtype != DWT2_F32 ||
+            f.band_dtype != c.band_dtype)
+            return DWT2_ERR_INVALID_ARG;
+    }
+    {   // the buffers each pair touches: the forward reads the finer `full` and
+        // writes both levels' bands and the coarser ll; the inverse the reverse
+        std::vector<Access> v;
+        v.reserve(8 * (size_t)(n > 0 ? n : 0));
+        for (int i = 0; i < n; ++i) {
+            const dwt2_level_job &f = jobs[2 * i], &c = jobs[2 * i + 1];
+            const int fx = f.width / 2, fy = f.height / 2, cx = c.width / 2, cy = c.height / 2;
+            v.push_back({region_of(f.full, f.height, f.width, f.full_pitch, f.full_dtype), 2 * i,
+                         INV});
+            v.push_back({region_of(f.hl, fy, fx, f.band_pitch, f.band_dtype), 2 * i, !INV});
+            v.push_back({region_of(f.lh, fy, fx, f.band_pitch, f.band_dtype), 2 * i, !INV});
+            v.push_back({region_of(f.hh, fy, fx, f.band_pitch, f.band_dtype), 2 * i, !INV});
+            v.push_back({region_of(c.ll, cy, cx, c.ll_pitch, c.ll_dtype), 2 * i + 1, !INV});
+            v.push_back({region_of(c.hl, cy, cx, c.band_pitch, c.band_dtype), 2 * i + 1, !INV});
+            v.push_back({region_of(c.lh, cy, cx, c.band_pitch, c.band_dtype), 2 * i + 1, !INV});
+            v.push_back({region_of(c.hh, cy, cx, c.band_pitch, c.band_dtype), 2 * i + 1, !INV});
+        }
+        if (cross_conflict(v)) return DWT2_ERR_INVALID_ARG;
+    }
+    std::vector<HeadKey> keys(n > 0 ? n : 1);
+    std::vector<char> done(n > 0 ? n : 1);
+    for (int i = 0; i < n; ++i) {
+        const dwt2_level_job &f = jobs[2 * i], &c = jobs[2 * i + 1];
+        keys[i] = INV ? HeadKey{f.band_dtype, c.ll_dtype == DWT2_F32, f.full_dtype == DWT2_F32}
+                      : HeadKey{f.band_dtype, f.full_dtype == DWT2_F32, c.ll_dtype == DWT2_F32};
+        done[i] = false;
+    }
+    int st = DWT2_OK;
+    for (int g = 0; g < n && st == DWT2_OK; ++g) {   // one group per distinct key
+        if (done[g]) continue;
+        const HeadKey key = keys[g];
+        typename std::conditional<INV, InvHeadBatch, FwdHeadBatch>::type b;
+        b.n = 0;
+        b.tile_start[0] = 0;
+        for (int i = g; i <= n && st == DWT2_OK; ++i) {
+            if (i < n && !done[i] && keys[i] == key) {
+                const dwt2_level_job &f = jobs[2 * i], &c = jobs[2 * i + 1];
+                int tiles;
+                if constexpr (INV) {
+                    InvHead &hd = b.h[b.n];
+                    hd.l2 = inv_params(c.ll, c.ll_pitch, c.ll_dtype, c.hl, c.lh, c.hh,
+                                       c.band_pitch, c.band_dtype, c.full, c.full_pitch,
+                                       c.full_dtype, c.width, c.height, wavelet, 0);
+                    hd.l1 = inv_params(f.ll, f.ll_pitch, f.ll_dtype, f.hl, f.lh, f.hh,
+                                       f.band_pitch, f.band_dtype, f.full, f.full_pitch,
+                                       f.full_dtype, f.width, f.height, wavelet, 0);
+                    hd.tiles_x = (hd.l1.nqx + FwdHeadGeom::IOX1 - 1) / FwdHeadGeom::IOX1;
+                    hd.tiles_y = (hd.l1.nqy + FwdHeadGeom::IOY1 - 1) / FwdHeadGeom::IOY1;
+                    tiles = hd.tiles_x * hd.tiles_y;
+                } else {
+                    FwdHead &hd = b.h[b.n];
+                    hd.l1 = fwd_params(f.full, f.full_pitch, f.full_dtype, f.width, f.height,
+                                       f.ll, f.ll_pitch, f.ll_dtype, f.hl, f.lh, f.hh,
+                                       f.band_pitch, f.band_dtype, wavelet, 0);
+                    hd.l2 = fwd_params(c.full, c.full_pitch, c.full_dtype, c.width, c.height,
+                                       c.ll, c.ll_pitch, c.ll_dtype, c.hl, c.lh, c.hh,
+                                       c.band_pitch, c.band_dtype, wavelet, 0);
+                    hd.tiles_x = (hd.l2.nqx + FwdHeadGeom::FOX2 - 1) / FwdHeadGeom::FOX2;
+                    hd.tiles_y = (hd.l2.nqy + FwdHeadGeom::FOY2 - 1) / FwdHeadGeom::FOY2;
+                    tiles = hd.tiles_x * hd.tiles_y;
+                }
+                if ((int64_t)b.tile_start[b.n] + tiles > (int64_t)INT32_MAX) {
+                    st = DWT2_ERR_INVALID_ARG;
+                    break;
+                }
+                b.tile_start[b.n + 1] = b.tile_start[b.n] + tiles;
+                ++b.n;
+                done[i] = true;
+            }
+            if (b.n > 0 && (b.n == kHeadBatchMax || i == n)) {
+                hipError_t e;
+                if constexpr (INV)
+                    e = inv_head_batch_table(key.band_dt)[wavelet][scheme][key.a_f32][key.b_f32](
+                        b, stream);
+                else
+                    e = fwd_head_batch_table(key.band_dt)[wavelet][scheme][key.a_f32][key.b_f32](
+                        b, stream);
+                if (e != hipSuccess) st = hip_fail(e);
+                b.n = 0;
+            }
+        }
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1266,6 +1389,16 @@ int dwt2_forward_level_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet
 int dwt2_inverse_level_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
                              dwt2_scheme scheme, const int32_t *class_tiles, hipStream_t stream) {
     return level_batch<true>(jobs, n, wavelet, scheme, class_tiles, stream);
+}
+
+int dwt2_forward_head_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                            dwt2_scheme scheme, hipStream_t stream) {
+    return head_batch<false>(jobs, n, wavelet, scheme, stream);
+}
+
+int dwt2_inverse_head_batch(const dwt2_level_job *jobs, int32_t n, dwt2_wavelet wavelet,
+                            dwt2_scheme scheme, hipStream_t stream) {
+    return head_batch<true>(jobs, n, wavelet, scheme, stream);
 }
 
 }  // extern "C"

@@ -373,4 +373,42 @@ __global__ __launch_bounds__(64 * WAVES, kTableHeadWavesPerSimd<WAVES>) void inv
     }
 }
 
+// Heads of independent images in one launch, with their parameters in the
+// kernel arguments (continuous batching: a different set every call), as the
+// level batches: up to kHeadBatchMax heads of one set of storage types;
+// tile_start[i] is the first global tile of head i (tile_start[n] the total).
+// One workgroup per tile.
+constexpr int kHeadBatchMax = 18;
+
+struct FwdHeadBatch {
+    int32_t n;
+    int32_t tile_start[kHeadBatchMax + 1];
+    FwdHead h[kHeadBatchMax];
+};
+struct InvHeadBatch {
+    int32_t n;
+    int32_t tile_start[kHeadBatchMax + 1];
+    InvHead h[kHeadBatchMax];
+};
+static_assert(sizeof(FwdHeadBatch) <= 4096 && sizeof(InvHeadBatch) <= 4096,
+              "kernel argument limit");
+
+template <int WV, int SCH, int ROWS, int WAVES, typename TIN, typename TLL, typename TB>
+__global__ __launch_bounds__(64 * WAVES, kTableHeadWavesPerSimd<WAVES>) void fwd_head_batch_kernel(
+    FwdHeadBatch bt) {
+    __shared__ FwdHeadLds<ROWS, WAVES> lds;
+    const int t = block_tile();
+    const int i = batch_image(bt, t);
+    fwd_head_tile<WV, SCH, ROWS, WAVES, TIN, TLL, TB>(bt.h[i], t - bt.tile_start[i], lds);
+}
+
+template <int WV, int SCH, int ROWS, int WAVES, typename TLL, typename TB, typename TOUT>
+__global__ __launch_bounds__(64 * WAVES, kTableHeadWavesPerSimd<WAVES>) void inv_head_batch_kernel(
+    InvHeadBatch bt) {
+    __shared__ InvHeadLds<ROWS, WAVES> lds;
+    const int t = block_tile();
+    const int i = batch_image(bt, t);
+    inv_head_tile<WV, SCH, ROWS, WAVES, TLL, TB, TOUT>(bt.h[i], t - bt.tile_start[i], lds);
+}
+
 }  // namespace dwt2

@@ -371,6 +371,54 @@ constexpr InvHeadPlanTable make_inv_head_plan_table() {
              {inv_head_plan_types<T, CDF53, NONSEP>(), inv_head_plan_types<T, CDF53, SEP>()}}};
 }
 
+// Head level batches (kernel-argument tables), indexed as the single-image
+// head tables.
+using FwdHeadBatchLauncher = hipError_t (*)(const FwdHeadBatch &, hipStream_t);
+using InvHeadBatchLauncher = hipError_t (*)(const InvHeadBatch &, hipStream_t);
+
+template <int WV, int SCH, typename TIN, typename TLL, typename T>
+hipError_t launch_fwd_head_batch(const FwdHeadBatch &b, hipStream_t s) {
+    const int grid = b.tile_start[b.n];
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fwd_head_batch_kernel<WV, SCH, kHeadRows, kHeadWaves, TIN, TLL, T>),
+                       dim3(grid), dim3(64 * kHeadWaves), 0, s, b);
+    return hipGetLastError();
+}
+template <int WV, int SCH, typename TLL, typename T, typename TOUT>
+hipError_t launch_inv_head_batch(const InvHeadBatch &b, hipStream_t s) {
+    const int grid = b.tile_start[b.n];
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((inv_head_batch_kernel<WV, SCH, kHeadRows, kHeadWaves, TLL, T, TOUT>),
+                       dim3(grid), dim3(64 * kHeadWaves), 0, s, b);
+    return hipGetLastError();
+}
+
+using FwdHeadBatchTable = std::array<std::array<std::array<std::array<FwdHeadBatchLauncher, 2>, 2>, 2>, 2>;
+using InvHeadBatchTable = std::array<std::array<std::array<std::array<InvHeadBatchLauncher, 2>, 2>, 2>, 2>;
+
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<FwdHeadBatchLauncher, 2>, 2> fwd_head_batch_types() {
+    return {{{&launch_fwd_head_batch<WV, SCH, T, T, T>, &launch_fwd_head_batch<WV, SCH, T, float, T>},
+             {&launch_fwd_head_batch<WV, SCH, float, T, T>,
+              &launch_fwd_head_batch<WV, SCH, float, float, T>}}};
+}
+template <typename T, int WV, int SCH>
+constexpr std::array<std::array<InvHeadBatchLauncher, 2>, 2> inv_head_batch_types() {
+    return {{{&launch_inv_head_batch<WV, SCH, T, T, T>, &launch_inv_head_batch<WV, SCH, T, T, float>},
+             {&launch_inv_head_batch<WV, SCH, float, T, T>,
+              &launch_inv_head_batch<WV, SCH, float, T, float>}}};
+}
+template <typename T>
+constexpr FwdHeadBatchTable make_fwd_head_batch_table() {
+    return {{{fwd_head_batch_types<T, CDF97, NONSEP>(), fwd_head_batch_types<T, CDF97, SEP>()},
+             {fwd_head_batch_types<T, CDF53, NONSEP>(), fwd_head_batch_types<T, CDF53, SEP>()}}};
+}
+template <typename T>
+constexpr InvHeadBatchTable make_inv_head_batch_table() {
+    return {{{inv_head_batch_types<T, CDF97, NONSEP>(), inv_head_batch_types<T, CDF97, SEP>()},
+             {inv_head_batch_types<T, CDF53, NONSEP>(), inv_head_batch_types<T, CDF53, SEP>()}}};
+}
+
 // The exchange ablation (NONSEP_LDS, SEP_LDS): FP32 level kernels only, index [wavelet][scheme - NONSEP_LDS][config].
 using FwdLdsTable = std::array<std::array<std::array<FwdLauncher, kNumTiles>, 2>, 2>;
 using InvLdsTable = std::array<std::array<std::array<InvLauncher, kNumTiles>, 2>, 2>;
@@ -414,6 +462,8 @@ extern FwdHeadTable kFwdHeadF32, kFwdHeadF16, kFwdHeadBF16;
 extern InvHeadTable kInvHeadF32, kInvHeadF16, kInvHeadBF16;
 extern FwdHeadPlanTable kFwdHeadPlanF32, kFwdHeadPlanF16, kFwdHeadPlanBF16;
 extern InvHeadPlanTable kInvHeadPlanF32, kInvHeadPlanF16, kInvHeadPlanBF16;
+extern FwdHeadBatchTable kFwdHeadBatchF32, kFwdHeadBatchF16, kFwdHeadBatchBF16;
+extern InvHeadBatchTable kInvHeadBatchF32, kInvHeadBatchF16, kInvHeadBatchBF16;
 extern InvTailTable kInvTailF32, kInvTailF16, kInvTailBF16;
 extern FwdLdsTable kFwdLds;
 extern InvLdsTable kInvLds;

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdHeadTable kFwdHeadBF16 = make_fwd_head_table<bf16_t>();
+FwdHeadBatchTable kFwdHeadBatchBF16 = make_fwd_head_batch_table<bf16_t>();
 }  // namespace dwt2

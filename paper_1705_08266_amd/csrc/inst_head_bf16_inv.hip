@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvHeadTable kInvHeadBF16 = make_inv_head_table<bf16_t>();
+InvHeadBatchTable kInvHeadBatchBF16 = make_inv_head_batch_table<bf16_t>();
 }  // namespace dwt2

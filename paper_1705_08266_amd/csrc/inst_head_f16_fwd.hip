@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdHeadTable kFwdHeadF16 = make_fwd_head_table<__half>();
+FwdHeadBatchTable kFwdHeadBatchF16 = make_fwd_head_batch_table<__half>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvHeadTable kInvHeadF16 = make_inv_head_table<__half>();
+InvHeadBatchTable kInvHeadBatchF16 = make_inv_head_batch_table<__half>();
 }  // namespace dwt2

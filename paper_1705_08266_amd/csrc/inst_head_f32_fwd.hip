@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 FwdHeadTable kFwdHeadF32 = make_fwd_head_table<float>();
+FwdHeadBatchTable kFwdHeadBatchF32 = make_fwd_head_batch_table<float>();
 }  // namespace dwt2

@@ -4,4 +4,5 @@
 
 namespace dwt2 {
 InvHeadTable kInvHeadF32 = make_inv_head_table<float>();
+InvHeadBatchTable kInvHeadBatchF32 = make_inv_head_batch_table<float>();
 }  // namespace dwt2

@@ -2,11 +2,15 @@
 
 Each request is one image (forward) or one Mallat pyramid (inverse) with its
 own level count. The loop works in iterations: an iteration advances every
-active request by exactly one level, enqueued as a few batched launches
-(dwt2_forward_level_batch / dwt2_inverse_level_batch, grouped by size class
-and storage types inside the library). New arrivals join at the next
-iteration and finished requests leave, so large and small requests share the
-device without a small one waiting for a large one to finish all its levels.
+active request by one step, enqueued as a few batched launches grouped by
+size class and storage types inside the library. A step is one level
+(dwt2_forward_level_batch / dwt2_inverse_level_batch) or, with fused heads
+(the default), two consecutive levels in one head launch
+(dwt2_forward_head_batch / dwt2_inverse_head_batch), paired from the finest
+level up, which keeps the band between them on chip and halves the steps. New
+arrivals join at the next iteration and finished requests leave, so large and
+small requests share the device without a small one waiting for a large one
+to finish all its levels.
 
 Admission is first-come first-served under an HBM budget: a request holds its
 input, its output pyramid and its FP32 intermediate low-low buffers from
@@ -25,6 +29,7 @@ import collections
 import ctypes
 import dataclasses
 import fractions
+import gc
 import math
 import time
 
@@ -65,14 +70,53 @@ def request_bytes(req: Request, dtype: int = _lib.F16) -> int:
 
 
 class _Active:
-    __slots__ = ("req", "bytes", "next_level", "t_admit", "payload")
+    __slots__ = ("req", "bytes", "next_level", "t_admit", "payload", "steps", "step_px")
 
-    def __init__(self, req, nbytes, t_admit):
+    def __init__(self, req, nbytes, t_admit, fuse_heads=False):
         self.req = req
         self.bytes = nbytes
-        self.next_level = 0          # levels already enqueued
+        self.next_level = 0          # steps already enqueued (levels without fused heads)
         self.t_admit = t_admit
         self.payload = None
+        # per step, the number of levels it runs and the input pixels of its
+        # finest level (request_steps, computed inline: this runs per admission)
+        L, W, H = req.levels, req.width, req.height
+        sizes = [2] * (L // 2) + [1] * (L % 2) if fuse_heads else [1] * L
+        if req.inverse:
+            sizes.reverse()
+        self.steps = sizes
+        px, top = [], (L if req.inverse else 1)
+        for n in sizes:
+            j = top - n + 1 if req.inverse else top      # finest level of the step
+            px.append((W >> (j - 1)) * (H >> (j - 1)))
+            top = top - n if req.inverse else top + n
+        self.step_px = px
+
+
+def request_steps(levels: int, inverse: bool, fuse_heads: bool = False):
+    """The launches of one request in execution order, each a tuple of the
+    levels it runs: one level, or with fuse_heads two consecutive levels in
+    one head launch, paired from the finest level up ((1, 2), (3, 4), ...; an
+    odd top level runs alone). A forward runs finest first; an inverse runs
+    coarsest first, a pair as (j + 1, j)."""
+    groups, j = [], 1
+    while j <= levels:
+        if fuse_heads and j + 1 <= levels:
+            groups.append((j, j + 1))
+            j += 2
+        else:
+            groups.append((j,))
+            j += 1
+    if inverse:
+        return [tuple(reversed(g)) for g in reversed(groups)]
+    return groups
+
+
+def step_pixels(req: Request, step: int, fuse_heads: bool = False) -> int:
+    """Input pixels of the finest level that a request's step-th launch
+    (0-based, execution order) runs: the measure of its work."""
+    j = min(request_steps(req.levels, req.inverse, fuse_heads)[step])
+    return (req.width >> (j - 1)) * (req.height >> (j - 1))
 
 
 def level_pixels(req: Request, level: int) -> int:
@@ -89,19 +133,23 @@ class Scheduler:
 
     offer(req)        queue an arrived request (False if it can never fit)
     admit(now)        move queue heads into the active set while they fit
-    iteration()       the active requests to advance by one level now: all of
+    iteration()       the active requests to advance by one step now: all of
                       them, or with max_iteration_pixels the oldest ones whose
-                      level inputs add up to at most that many pixels (always
-                      at least the oldest), so that one iteration's device
-                      time stays bounded however many requests are admitted
+                      steps' finest level inputs add up to at most that many
+                      pixels (always at least the oldest), so that one
+                      iteration's device time stays bounded however many
+                      requests are admitted
     finish_iteration  advance them; returns those that have enqueued their
-                      last level (their bytes stay held until release())
+                      last step (their bytes stay held until release())
+
+    A step is one level, or with fuse_heads a pair of levels (request_steps).
     release(a)        return a finished request's bytes to the budget
     """
 
     def __init__(self, budget_bytes: int, max_active: int = 1 << 30, bytes_fn=request_bytes,
-                 max_iteration_pixels: int | None = None):
+                 max_iteration_pixels: int | None = None, fuse_heads: bool = False):
         self.budget = int(budget_bytes)
+        self.fuse_heads = bool(fuse_heads)
         self.max_active = int(max_active)
         self.max_iteration_pixels = max_iteration_pixels
         self.bytes_fn = bytes_fn
@@ -126,7 +174,7 @@ class Scheduler:
             if self.used + nb > self.budget:
                 break                          # strict FIFO: no overtaking
             self.queue.popleft()
-            a = _Active(req, nb, now)
+            a = _Active(req, nb, now, self.fuse_heads)
             self.active.append(a)
             self.used += nb
             admitted.append(a)
@@ -138,7 +186,7 @@ class Scheduler:
             return list(self.active)
         out, px = [], 0
         for a in self.active:                  # admission order: oldest first
-            p = level_pixels(a.req, a.next_level)
+            p = a.step_px[a.next_level]
             if out and px + p > self.max_iteration_pixels:
                 break
             out.append(a)
@@ -149,7 +197,7 @@ class Scheduler:
         done = []
         for a in advanced:
             a.next_level += 1
-            if a.next_level == a.req.levels:
+            if a.next_level == len(a.step_px):
                 done.append(a)
         if done:
             ids = {id(a) for a in done}
@@ -179,7 +227,32 @@ def _job(full, ll, hl, lh, hh, width, height, dtcode):
     return j
 
 
-def level_jobs(src, out, ws0, ws1, levels, inverse):
+def ll_slots(width: int, height: int, levels: int, fuse_heads: bool = False):
+    """Where each intermediate low-low band LL_k (1 <= k < levels, the output
+    of level k's forward) lives: k -> (buffer 0 or 1, offset in floats).
+
+    One level per step: LL_k alternates between ws0 and ws1 at offset 0 (a
+    level reads one and writes the other). With fused heads (request_steps),
+    the bands that steps store, LL_2, LL_4, ..., alternate between ws1 and ws0,
+    so that a step never writes the buffer it reads; the band inside a pair,
+    LL_k for odd k, is never accessed but needs a place of its own: ws0 at 0
+    for LL_1, else ws0 just past the stored band there (LL_(k-1) is at most
+    (W >> (k-1)) * (H >> (k-1)) floats). ws0 holds (W/2)(H/2) floats and ws1
+    (W/4)(H/4), which is enough for every slot."""
+    slots = {}
+    for k in range(1, levels):
+        if not fuse_heads:
+            slots[k] = ((k - 1) % 2, 0)
+        elif k % 2 == 0:
+            slots[k] = (1 if (k // 2) % 2 == 1 else 0, 0)
+        elif k == 1:
+            slots[k] = (0, 0)
+        else:
+            slots[k] = (0, (width >> (k - 1)) * (height >> (k - 1)))
+    return slots
+
+
+def level_jobs(src, out, ws0, ws1, levels, inverse, fuse_heads=False):
     """Per-level job descriptors of one request, in execution order.
 
     Forward: level j reads the image (j = 1) or the previous low-low band and
@@ -187,8 +260,10 @@ def level_jobs(src, out, ws0, ws1, levels, inverse):
     low-low band to an FP32 buffer (or to the top-left of `out` at the last
     level). Inverse: levels L..1 mirror that, reading the pyramid `src` and
     writing the image to `out`. ws0 holds a quarter of the image, ws1 a
-    sixteenth; consecutive levels alternate between them. Pointers are
-    computed directly (this runs once per admitted request).
+    sixteenth; the FP32 bands take the places ll_slots gives (with
+    fuse_heads, a layout in which every pair of request_steps can run as one
+    head launch). Pointers are computed directly (this runs once per admitted
+    request).
     """
     from . import _dtype_code
     H, W = src.shape
@@ -200,6 +275,12 @@ def level_jobs(src, out, ws0, ws1, levels, inverse):
     pyr = (src if inverse else out).data_ptr()
     img = (out if inverse else src).data_ptr()
     ws = (ws0.data_ptr(), ws1.data_ptr())
+    slots = ll_slots(W, H, levels, fuse_heads)
+
+    def band(k):                     # address of LL_k
+        b, off = slots[k]
+        return ws[b] + 4 * off
+
     jobs = (_lib.LevelJob * levels)()
     order = range(levels, 0, -1) if inverse else range(1, levels + 1)
     for k, j in enumerate(order):
@@ -209,11 +290,11 @@ def level_jobs(src, out, ws0, ws1, levels, inverse):
         if j == 1:
             job.full, job.full_pitch, job.full_dtype = img, P, dt
         else:
-            job.full, job.full_pitch, job.full_dtype = ws[(j - 2) % 2], w, _lib.F32
+            job.full, job.full_pitch, job.full_dtype = band(j - 1), w, _lib.F32
         if j == levels:
             job.ll, job.ll_pitch, job.ll_dtype = pyr, P, dt
         else:
-            job.ll, job.ll_pitch, job.ll_dtype = ws[(j - 1) % 2], w2, _lib.F32
+            job.ll, job.ll_pitch, job.ll_dtype = band(j), w2, _lib.F32
         job.hl = pyr + e * w2
         job.lh = pyr + e * h2 * P
         job.hh = pyr + e * (h2 * P + w2)
@@ -265,11 +346,13 @@ class Server:
 
     def __init__(self, budget_bytes=64 << 30, max_active=1 << 30, wavelet="cdf97",
                  scheme="nonseparable", dtype="f16", class_tiles=None, max_inflight=2,
-                 max_iteration_pixels=None):
+                 max_iteration_pixels=None, fuse_heads=True):
         self.dtype = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[dtype]
+        self.fuse_heads = bool(fuse_heads)
         self.sched = Scheduler(budget_bytes, max_active,
                                bytes_fn=lambda r: request_bytes(r, self.dtype),
-                               max_iteration_pixels=max_iteration_pixels)
+                               max_iteration_pixels=max_iteration_pixels,
+                               fuse_heads=self.fuse_heads)
         self.wavelet = _wavelet(wavelet)
         self.scheme = _scheme(scheme)
         self.class_tiles = (None if class_tiles is None else
@@ -289,20 +372,37 @@ class Server:
         n1 = (req.width // 4) * (req.height // 4) if req.levels > 2 else 1
         ws0 = torch.empty(n0, dtype=torch.float32, device=src.device)
         ws1 = torch.empty(n1, dtype=torch.float32, device=src.device)
-        a.payload = {"out": out, "ws": (ws0, ws1),
-                     "jobs": level_jobs(src, out, ws0, ws1, req.levels, req.inverse)}
+        jobs = level_jobs(src, out, ws0, ws1, req.levels, req.inverse, self.fuse_heads)
+        # first job (execution order) of each step
+        first, k = [], 0
+        for n in a.steps:
+            first.append(k)
+            k += n
+        a.payload = {"out": out, "ws": (ws0, ws1), "jobs": jobs, "first": first}
 
     def _enqueue(self, advanced, stream):
         lib = load()
-        fwd = [a.payload["jobs"][a.next_level] for a in advanced if not a.req.inverse]
-        inv = [a.payload["jobs"][a.next_level] for a in advanced if a.req.inverse]
-        for jobs, fn, name in ((fwd, lib.dwt2_forward_level_batch, "dwt2_forward_level_batch"),
-                               (inv, lib.dwt2_inverse_level_batch, "dwt2_inverse_level_batch")):
-            if jobs:
-                arr = (_lib.LevelJob * len(jobs))(*jobs)
-                _lib.check(fn(arr, len(jobs), self.wavelet, self.scheme, self.class_tiles,
-                              stream), name)
-                self.launch_calls += 1
+        calls = {(inv, n): [] for inv in (False, True) for n in (1, 2)}
+        for a in advanced:
+            jobs, k = a.payload["jobs"], a.payload["first"][a.next_level]
+            n, inv = a.steps[a.next_level], a.req.inverse
+            if n == 1:
+                calls[(inv, 1)].append(jobs[k])
+            else:                        # a head pair as (finer, coarser) level
+                calls[(inv, 2)] += (jobs[k + 1], jobs[k]) if inv else (jobs[k], jobs[k + 1])
+        fns = {(False, 1): ("dwt2_forward_level_batch", True),
+               (True, 1): ("dwt2_inverse_level_batch", True),
+               (False, 2): ("dwt2_forward_head_batch", False),
+               (True, 2): ("dwt2_inverse_head_batch", False)}
+        for key, jobs in calls.items():
+            if not jobs:
+                continue
+            name, tiles = fns[key]
+            arr = (_lib.LevelJob * len(jobs))(*jobs)
+            n = len(jobs) // key[1]
+            args = (arr, n, self.wavelet, self.scheme) + ((self.class_tiles,) if tiles else ())
+            _lib.check(getattr(lib, name)(*args, stream), name)
+            self.launch_calls += 1
 
     def run(self, requests, inputs, keep_outputs=False, realtime=True):
         """Serve `requests` (sorted by arrival). With realtime=False every
@@ -336,35 +436,44 @@ class Server:
                 a.payload = None
                 self.sched.release(a)
 
-        while pending or not self.sched.idle or inflight:
-            now = time.perf_counter() - t0
-            while pending and (not realtime or pending[0].arrival_s <= now):
-                r = pending.popleft()
-                if not self.sched.offer(r):            # can never fit the budget
-                    results.append(Result(r.rid, r.arrival_s, float("nan"), None,
-                                          rejected=True))
-            for a in self.sched.admit(now):
-                self._allocate(a, inputs, torch)
-            advanced = self.sched.iteration()
-            if advanced:
-                ev0 = torch.cuda.Event(enable_timing=True)
-                ev0.record(stream)
-                self._enqueue(advanced, sptr)
-                done = self.sched.finish_iteration(advanced)
-                ev = torch.cuda.Event(enable_timing=True)
-                ev.record(stream)
-                inflight.append((ev0, ev, done))
-                self.iterations += 1
-            # observe completions; keep at most max_inflight iterations queued
-            while inflight and (len(inflight) > self.max_inflight or inflight[0][1].query()
-                                or (not advanced and not pending)):
-                ev0, ev, done = inflight.popleft()
-                ev.synchronize()
-                retire(ev0, ev, done)
-            if not advanced and not inflight and pending and realtime:
-                wait = pending[0].arrival_s - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 1e-3))
+        # The loop's objects are freed by reference counting; the cyclic
+        # collector is paused for the run, since its passes over the many live
+        # objects (requests, buffers, events) stall iterations by tens of ms.
+        gc_was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            while pending or not self.sched.idle or inflight:
+                now = time.perf_counter() - t0
+                while pending and (not realtime or pending[0].arrival_s <= now):
+                    r = pending.popleft()
+                    if not self.sched.offer(r):            # can never fit the budget
+                        results.append(Result(r.rid, r.arrival_s, float("nan"), None,
+                                              rejected=True))
+                for a in self.sched.admit(now):
+                    self._allocate(a, inputs, torch)
+                advanced = self.sched.iteration()
+                if advanced:
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev0.record(stream)
+                    self._enqueue(advanced, sptr)
+                    done = self.sched.finish_iteration(advanced)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(stream)
+                    inflight.append((ev0, ev, done))
+                    self.iterations += 1
+                # observe completions; keep at most max_inflight iterations queued
+                while inflight and (len(inflight) > self.max_inflight or inflight[0][1].query()
+                                    or (not advanced and not pending)):
+                    ev0, ev, done = inflight.popleft()
+                    ev.synchronize()
+                    retire(ev0, ev, done)
+                if not advanced and not inflight and pending and realtime:
+                    wait = pending[0].arrival_s - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 1e-3))
+        finally:
+            if gc_was_enabled:
+                gc.enable()
         return results
 
 

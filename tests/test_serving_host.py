@@ -229,3 +229,125 @@ def test_iteration_pixel_cap_advances_the_oldest_first():
     it = sch.iteration()
     assert [a.req.rid for a in it] == [2]                 # alone it may exceed the cap
     assert sv.Scheduler(1 << 40).max_iteration_pixels is None
+
+
+def test_request_steps_pair_levels_from_the_finest():
+    assert sv.request_steps(5, False, True) == [(1, 2), (3, 4), (5,)]
+    assert sv.request_steps(5, True, True) == [(5,), (4, 3), (2, 1)]
+    assert sv.request_steps(4, True, True) == [(4, 3), (2, 1)]
+    assert sv.request_steps(1, False, True) == [(1,)] == sv.request_steps(1, True, True)
+    assert sv.request_steps(3, False, False) == [(1,), (2,), (3,)]
+    assert sv.request_steps(3, True, False) == [(3,), (2,), (1,)]
+    for L in range(1, 7):
+        for inv in (False, True):
+            steps = sv.request_steps(L, inv, True)
+            assert sorted(j for g in steps for j in g) == list(range(1, L + 1))
+            assert len(steps) == (L + 1) // 2
+
+
+def test_fused_scheduler_finishes_in_half_the_iterations_and_caps_by_finest_level():
+    reqs = [sv.Request(0, 0.0, 1024, 1024, 5, False), sv.Request(1, 0.0, 512, 512, 4, True)]
+    assert [sv.step_pixels(reqs[0], k, True) for k in range(3)] == [1024 ** 2, 256 ** 2, 64 ** 2]
+    assert [sv.step_pixels(reqs[1], k, True) for k in range(2)] == [128 ** 2, 512 ** 2]
+    sch = sv.Scheduler(1 << 40, fuse_heads=True)
+    for r in reqs:
+        assert sch.offer(r)
+    sch.admit(0.0)
+    finished = {}
+    for it in range(1, 10):
+        for a in sch.finish_iteration(sch.iteration()):
+            finished[a.req.rid] = it
+        if sch.idle:
+            break
+    assert finished == {0: 3, 1: 2}
+    capped = sv.Scheduler(1 << 40, max_iteration_pixels=1024 ** 2, fuse_heads=True)
+    for r in reqs:
+        capped.offer(r)
+    capped.admit(0.0)
+    assert [a.req.rid for a in capped.iteration()] == [0]      # 1024^2 + 128^2 > cap
+
+
+def test_head_batch_rejects_bad_pairs_before_any_launch():
+    lib = _lib.load()
+    F = 0x10000000
+    E, U = _lib.ERR_INVALID_ARG, _lib.ERR_UNSUPPORTED
+
+    def job(full, full_dt, ll, ll_dt, bands, w, h):
+        j = _lib.LevelJob()
+        j.full, j.full_pitch, j.full_dtype = full, w, full_dt
+        j.ll, j.ll_pitch, j.ll_dtype = ll, w // 2, ll_dt
+        j.hl, j.lh, j.hh = bands, bands + (1 << 20), bands + (2 << 20)
+        j.band_pitch, j.band_dtype = w // 2, _lib.F32
+        j.width, j.height = w, h
+        return j
+
+    mid = F + (1 << 26)
+    fine = job(F, _lib.F32, mid, _lib.F32, F + (2 << 26), 64, 64)
+    coarse = job(mid, _lib.F32, F + (3 << 26), _lib.F32, F + (4 << 26), 32, 32)
+
+    def call(pair, scheme=0, fn="dwt2_forward_head_batch"):
+        arr = (_lib.LevelJob * len(pair))(*pair)
+        return getattr(lib, fn)(arr, len(pair) // 2, 0, scheme, None)
+
+    assert lib.dwt2_forward_head_batch(None, 0, 0, 0, None) == 0            # nothing to do
+    assert call([fine, coarse], scheme=2) == U                              # LDS ablation
+    bad = job(mid, _lib.F32, F + (3 << 26), _lib.F32, F + (4 << 26), 32, 16)
+    assert call([fine, bad]) == E                                           # not half size
+    other = job(mid + 4096, _lib.F32, F + (3 << 26), _lib.F32, F + (4 << 26), 32, 32)
+    assert call([fine, other]) == E                                         # band not shared
+    half = job(F, _lib.F32, mid, _lib.F16, F + (2 << 26), 64, 64)
+    assert call([half, coarse]) == E                                        # band not FP32
+    clash = job(mid, _lib.F32, F + (2 << 26), _lib.F32, F + (4 << 26), 32, 32)
+    assert call([fine, clash]) == E                   # forward: coarse ll on fine hl, both written
+    out_on_band = job(F + (4 << 26), _lib.F32, mid, _lib.F32, F + (2 << 26), 64, 64)
+    assert call([out_on_band, coarse], fn="dwt2_inverse_head_batch") == E   # output on a read band
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_fused_layout_never_writes_what_a_step_reads(levels, inverse):
+    torch = pytest.importorskip("torch")
+    W, H = 512, 320
+    src = torch.zeros(H, W, dtype=torch.float16)
+    out = torch.zeros_like(src)
+    n0 = (W // 2) * (H // 2) if levels > 1 else 1
+    n1 = (W // 4) * (H // 4) if levels > 2 else 1
+    ws0, ws1 = torch.zeros(n0), torch.zeros(n1)
+    jobs = sv.level_jobs(src, out, ws0, ws1, levels, inverse, fuse_heads=True)
+    index = {(levels - k if inverse else k + 1): k for k in range(levels)}
+    bufs = [(ws0.data_ptr(), 4 * n0), (ws1.data_ptr(), 4 * n1)]
+
+    def span(ptr, rows, pitch, es):
+        return ptr, ptr + rows * pitch * es
+
+    def inside_ws(lo, hi):
+        return any(b <= lo and hi <= b + n for b, n in bufs)
+
+    def apart(a, b):
+        return a[1] <= b[0] or b[1] <= a[0]
+
+    for j in range(1, levels):                     # every FP32 band fits its buffer
+        jb = jobs[index[j]]
+        assert inside_ws(*span(jb.ll, jb.height // 2, jb.ll_pitch, 4))
+    for g in sv.request_steps(levels, inverse, True):
+        if len(g) == 1:
+            continue
+        fine, coarse = jobs[index[min(g)]], jobs[index[max(g)]]
+        assert fine.ll == coarse.full and fine.ll_pitch == coarse.full_pitch
+        first = span(fine.full, fine.height, fine.full_pitch, 2 if min(g) == 1 else 4)
+        last = span(coarse.ll, coarse.height // 2, coarse.ll_pitch,
+                    2 if max(g) == levels else 4)
+        assert apart(first, last)                 # the pair's input and output
+        mid = span(fine.ll, fine.height // 2, fine.ll_pitch, 4)
+        assert apart(mid, first) and apart(mid, last)
+
+
+def test_admitted_step_bookkeeping_matches_request_steps():
+    for L in range(1, 8):
+        for inv in (False, True):
+            for fuse in (False, True):
+                req = sv.Request(0, 0.0, 1 << 9, 3 << 8, L, inv)
+                a = sv._Active(req, 0, 0.0, fuse)
+                steps = sv.request_steps(L, inv, fuse)
+                assert a.steps == [len(g) for g in steps]
+                assert a.step_px == [sv.step_pixels(req, k, fuse) for k in range(len(steps))]
