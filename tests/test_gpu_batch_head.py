@@ -88,3 +88,19 @@ def test_head_batch_graph_replays_match_eager():
         torch.cuda.synchronize()
         for a, b in zip(eager, plan.outputs):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_head_batch_tiny_and_ragged_images(inverse):
+    sizes = [(4, 4), (8, 4), (4, 8), (12, 8), (36, 20), (260, 132), (116, 44), (232, 72)]
+    imgs = [torch.from_numpy(synthetic.uniform_image(h, w, seed=61 + i)).to("cuda")
+            for i, (w, h) in enumerate(sizes)]
+    print(f"case head batch tiny/ragged inverse={inverse}", flush=True)
+    srcs = [dwt.forward(x, "cdf97", 2) for x in imgs] if inverse else imgs
+    plan = (dwb.BatchPlan.inverse_of(srcs, 2, fuse_head=True) if inverse
+            else dwb.BatchPlan.forward(srcs, 2, fuse_head=True))
+    plan.run()
+    torch.cuda.synchronize()
+    for s, o in zip(srcs, plan.outputs):
+        single = dwt.inverse(s, "cdf97", 2) if inverse else dwt.forward(s, "cdf97", 2)
+        assert torch.equal(single, o), tuple(s.shape)
