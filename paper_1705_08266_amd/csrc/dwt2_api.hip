@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -235,7 +236,36 @@ struct TailPlan {
     int B, e[kTailMax];
 };
 
-TailPlan plan_fwd_tail(int F, int wavelet) {
+// Compute units of the current device (queried once per device).
+int device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
+// Block side of a tail whose block-owning level has nqx x nqy quads, given the
+// largest side that fits (fit): the smallest side whose grid still has at most
+// one workgroup per CU, and at least 2. Each workgroup's latency chain shortens with its
+// region, and the tail runs in one round, so up to that point smaller blocks
+// are faster; beyond it workgroups share CUs. Measured on both directions at
+// 2048^2 to 8192^2 (e.g. 4096^2, three levels: 11.9 -> 11.0 us forward with
+// 256 instead of 225 workgroups); the results do not depend on the block.
+int tail_block(int fit, int nqx, int nqy) {
+    const int64_t cus = device_cus();
+    int B = fit;
+    while (B > 2 && (int64_t)((nqx + B - 2) / (B - 1)) * ((nqy + B - 2) / (B - 1)) <= cus) --B;
+    return B;
+}
+
+TailPlan plan_fwd_tail(int F, int wavelet, int nqx_last, int nqy_last) {
     const int R = wavelet == DWT2_CDF97 ? 2 : 1;
     TailPlan t;
     t.e[F - 1] = 0;
@@ -247,14 +277,11 @@ TailPlan plan_fwd_tail(int F, int wavelet) {
         const int b = (lim - 2 * t.e[m]) >> (F - 1 - m);
         if (b < B) B = b;
     }
-    t.B = B;
+    t.B = tail_block(B, nqx_last, nqy_last);
     return t;
 }
 
-// Largest extent, in quads, of an inverse tail block at its finest level.
-constexpr int kInvTailFinestBlock = 28;
-
-TailPlan plan_inv_tail(int F, int wavelet) {
+TailPlan plan_inv_tail(int F, int wavelet, int nqx_first, int nqy_first) {
     const int R = wavelet == DWT2_CDF97 ? 2 : 1;
     TailPlan t;
     t.e[F - 1] = 0;
@@ -269,13 +296,10 @@ TailPlan plan_inv_tail(int F, int wavelet) {
         if (b < B) B = b;
     }
     // The largest block leaves most of the GPU idle (100 workgroups for the
-    // three-level tail at 4096^2, 15 for the two-level tail at 7680x4320).
-    // Blocks whose finest level spans at most 28 quads, about half the 64-lane
-    // window, spread the work over more workgroups with fewer active
-    // wavefronts each, which measured faster. Smaller blocks measured slower:
-    // every workgroup still loads and lifts its whole window.
-    if (B > (kInvTailFinestBlock >> (F - 1))) B = kInvTailFinestBlock >> (F - 1);
-    t.B = B;
+    // three-level tail at 4096^2): as the forward, the smallest block whose
+    // grid fits one workgroup per CU (4096^2: 10.4 -> 9.6 us against the
+    // earlier cap of 28 quads at the finest level).
+    t.B = tail_block(B, nqx_first, nqy_first);
     return t;
 }
 
@@ -949,7 +973,7 @@ int dwt2_forward_ex(const void *src, const dwt2_desc *src_d, void *coef, const d
     }
     if (k <= levels) {
         const int F = levels + 1 - k;
-        const TailPlan pl = plan_fwd_tail(F, wavelet);
+        const TailPlan pl = plan_fwd_tail(F, wavelet, tail.lv[F - 1].nqx, tail.lv[F - 1].nqy);
         tail.F = F;
         tail.B = pl.B;
         for (int m = 0; m < F; ++m) tail.e[m] = pl.e[m];
@@ -1016,7 +1040,7 @@ int dwt2_inverse_ex(const void *coef, const dwt2_desc *coef_d, void *dst, const 
             p.vec_out = aligned(out, out_pitch, out_dt, 2);
             if (j > k) continue;
             const int F = levels + 1 - k;
-            const TailPlan pl = plan_inv_tail(F, wavelet);
+            const TailPlan pl = plan_inv_tail(F, wavelet, tail.lv[0].nqx, tail.lv[0].nqy);
             tail.F = F;
             tail.B = pl.B;
             for (int m = 0; m < F; ++m) tail.e[m] = pl.e[m];
