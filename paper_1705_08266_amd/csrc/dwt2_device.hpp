@@ -245,11 +245,14 @@ __device__ __forceinline__ bool wave_all(bool c) {
 // ---- cross-lane shifts (DPP, wavefront-wide) ----------------------------------
 // from_right(v): lane l receives lane l+1's v (lane 63 receives 0).
 // from_left(v):  lane l receives lane l-1's v (lane 0 receives 0).
+// The zero for the lane without a source comes from the bound-control bit,
+// not from the instruction's old value, so no register has to be zeroed
+// before each shift.
 __device__ __forceinline__ float from_right(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_left(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 // ---- the register tile --------------------------------------------------------
