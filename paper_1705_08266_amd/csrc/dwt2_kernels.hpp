@@ -171,13 +171,26 @@ __device__ __forceinline__ void fwd_load_at(Quads<ROWS, QPL> &q, const FwdParams
     // all rows' first vectors, then (edge wavefronts only) the completion
     rsrc_t rows[2 * ROWS];
     float v[2 * ROWS][2 * QPL];
+    if (2 * qy0 >= 0 && 2 * (qy0 + ROWS) <= prm.h) {
+        // all rows inside the level (wavefront-uniform): step the row pointer
+        // instead of mirroring and multiplying per row, so that the loads
+        // issue sooner
+        const TIN *p = in + (int64_t)(2 * qy0) * prm.in_pitch;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int py = 2 * (qy0 + r);
-        rows[2 * r] = make_rsrc(in + (int64_t)mirror(py, prm.h) * prm.in_pitch, rb);
-        rows[2 * r + 1] = make_rsrc(in + (int64_t)mirror(py + 1, prm.h) * prm.in_pitch, rb);
-        load_vec<TIN, 2 * QPL>(rows[2 * r], cols.off_a, v[2 * r]);
-        load_vec<TIN, 2 * QPL>(rows[2 * r + 1], cols.off_a, v[2 * r + 1]);
+        for (int r = 0; r < 2 * ROWS; ++r) {
+            rows[r] = make_rsrc(p, rb);
+            load_vec<TIN, 2 * QPL>(rows[r], cols.off_a, v[r]);
+            p += prm.in_pitch;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int py = 2 * (qy0 + r);
+            rows[2 * r] = make_rsrc(in + (int64_t)mirror(py, prm.h) * prm.in_pitch, rb);
+            rows[2 * r + 1] = make_rsrc(in + (int64_t)mirror(py + 1, prm.h) * prm.in_pitch, rb);
+            load_vec<TIN, 2 * QPL>(rows[2 * r], cols.off_a, v[2 * r]);
+            load_vec<TIN, 2 * QPL>(rows[2 * r + 1], cols.off_a, v[2 * r + 1]);
+        }
     }
     if (!wave_all(cols.plain)) fix_cols<TIN>(rows, cols, v);
 #pragma unroll
