@@ -338,19 +338,39 @@ __device__ __forceinline__ void inv_load_at(Quads<ROWS, QPL> &q, const InvParams
     const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
     const uint32_t lb = (uint32_t)prm.nqx * (uint32_t)sizeof(TLL);
     rsrc_t rl[ROWS], rh[ROWS], rv[ROWS], rd[ROWS];   // LL, HL, LH, HH rows
+    if (qy0 >= 0 && 2 * (qy0 + ROWS) <= prm.h) {
+        // all rows inside the level (wavefront-uniform): both phases of quad
+        // row gy are band row gy; step the row pointers
+        const TLL *pl = ll + (int64_t)qy0 * prm.ll_pitch;
+        const int64_t ob = (int64_t)qy0 * prm.band_pitch;
+        const TB *ph = hl + ob, *pv = lh + ob, *pd = hh + ob;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int gy = qy0 + r;
-        const int64_t ye = mirror(2 * gy, prm.h) >> 1;
-        const int64_t yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
-        if constexpr (WITH_LL) rl[r] = make_rsrc(ll + ye * prm.ll_pitch, lb);
-        rh[r] = make_rsrc(hl + ye * prm.band_pitch, bb);
-        rv[r] = make_rsrc(lh + yo * prm.band_pitch, bb);
-        rd[r] = make_rsrc(hh + yo * prm.band_pitch, bb);
-        if constexpr (WITH_LL) load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
-        load_vec<TB, QPL>(rh[r], co.off_a, q.b[r]);
-        load_vec<TB, QPL>(rv[r], ce.off_a, q.c[r]);
-        load_vec<TB, QPL>(rd[r], co.off_a, q.d[r]);
+        for (int r = 0; r < ROWS; ++r) {
+            if constexpr (WITH_LL) rl[r] = make_rsrc(pl, lb);
+            rh[r] = make_rsrc(ph, bb);
+            rv[r] = make_rsrc(pv, bb);
+            rd[r] = make_rsrc(pd, bb);
+            if constexpr (WITH_LL) load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
+            load_vec<TB, QPL>(rh[r], co.off_a, q.b[r]);
+            load_vec<TB, QPL>(rv[r], ce.off_a, q.c[r]);
+            load_vec<TB, QPL>(rd[r], co.off_a, q.d[r]);
+            pl += prm.ll_pitch; ph += prm.band_pitch; pv += prm.band_pitch; pd += prm.band_pitch;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int gy = qy0 + r;
+            const int64_t ye = mirror(2 * gy, prm.h) >> 1;
+            const int64_t yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
+            if constexpr (WITH_LL) rl[r] = make_rsrc(ll + ye * prm.ll_pitch, lb);
+            rh[r] = make_rsrc(hl + ye * prm.band_pitch, bb);
+            rv[r] = make_rsrc(lh + yo * prm.band_pitch, bb);
+            rd[r] = make_rsrc(hh + yo * prm.band_pitch, bb);
+            if constexpr (WITH_LL) load_vec<TLL, QPL>(rl[r], cl.off_a, q.a[r]);
+            load_vec<TB, QPL>(rh[r], co.off_a, q.b[r]);
+            load_vec<TB, QPL>(rv[r], ce.off_a, q.c[r]);
+            load_vec<TB, QPL>(rd[r], co.off_a, q.d[r]);
+        }
     }
     if (!wave_all(plain)) {
         if constexpr (WITH_LL) fix_cols<TLL>(rl, cl, q.a);
