@@ -93,6 +93,14 @@ __device__ __forceinline__ rsrc_t row_rsrc(const void *base, int64_t row, int64_
                      (uint32_t)n * (uint32_t)sizeof(T));
 }
 
+// The same for a row whose element offset (row times pitch) the caller keeps:
+// loops over consecutive rows step the offset by the pitch instead of
+// multiplying per row.
+template <typename T>
+__device__ __forceinline__ rsrc_t row_at(const void *base, int64_t off, int n) {
+    return make_rsrc(static_cast<const T *>(base) + off, (uint32_t)n * (uint32_t)sizeof(T));
+}
+
 // F (the number of fused levels) is a template parameter so that the level
 // loop unrolls and every level's parameters load at kernel start.
 template <int WV, int SCH, int F, typename TIN, typename TLL, typename TB>
@@ -146,21 +154,20 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
         const uint32_t ob = (qx >= g.ox0 && qx < g.ox1) ? (uint32_t)qx * sizeof(TB) : kNoAccess;
         const uint32_t ol = (qx >= g.ox0 && qx < g.ox1) ? (uint32_t)qx * sizeof(TLL) : kNoAccess;
         const bool comp_x = qx >= g.cx0 && qx < g.cx1;
+        int64_t rb = (int64_t)qy0 * prm.band_pitch, rl = (int64_t)qy0 * prm.ll_pitch;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int gy = qy0 + r;
             const float va = q.a[r][0] * sLL;
             if (gy >= g.oy0 && gy < g.oy1) {   // wavefront-uniform
-                store_elem<TB>(row_rsrc<TB>(prm.hl, gy, prm.band_pitch, prm.nqx), ob,
-                               q.b[r][0] * sHL);
-                store_elem<TB>(row_rsrc<TB>(prm.lh, gy, prm.band_pitch, prm.nqx), ob,
-                               q.c[r][0] * sHL);
-                store_elem<TB>(row_rsrc<TB>(prm.hh, gy, prm.band_pitch, prm.nqx), ob,
-                               q.d[r][0] * sHH);
-                if (last) store_elem<TLL>(row_rsrc<TLL>(prm.ll, gy, prm.ll_pitch, prm.nqx), ol, va);
+                store_elem<TB>(row_at<TB>(prm.hl, rb, prm.nqx), ob, q.b[r][0] * sHL);
+                store_elem<TB>(row_at<TB>(prm.lh, rb, prm.nqx), ob, q.c[r][0] * sHL);
+                store_elem<TB>(row_at<TB>(prm.hh, rb, prm.nqx), ob, q.d[r][0] * sHH);
+                if (last) store_elem<TLL>(row_at<TLL>(prm.ll, rl, prm.nqx), ol, va);
             }
             if (!last && comp_x && gy >= g.cy0 && gy < g.cy1)
                 dst[(gy - g.cy0) * cw + (qx - g.cx0)] = va;
+            rb += prm.band_pitch; rl += prm.ll_pitch;
         }
         px0 = g.cx0; py0 = g.cy0; pw = cw; ph = g.cy1 - g.cy0;
         __syncthreads();   // this level's LL is complete before the next level reads it
@@ -204,15 +211,29 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
             const int xo = (mirror(2 * qx + 1, prm.w) - 1) >> 1;
             const int xl = clamp_to(xe, px0, pw);
             const uint32_t oe = (uint32_t)xe * sizeof(TB), oo = (uint32_t)xo * sizeof(TB);
+            if (qy0 >= 0 && 2 * (qy0 + ROWS) <= prm.h) {
+                // all rows inside the level (wavefront-uniform): both phases of
+                // quad row gy are band row gy
+                int64_t rb = (int64_t)qy0 * prm.band_pitch;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int gy = qy0 + r;
-                const int ye = mirror(2 * gy, prm.h) >> 1;
-                const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
-                q.a[r][0] = src[clamp_to(ye, py0, ph) * pw + xl];
-                q.b[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hl, ye, prm.band_pitch, prm.nqx), oo);
-                q.c[r][0] = load_elem<TB>(row_rsrc<TB>(prm.lh, yo, prm.band_pitch, prm.nqx), oe);
-                q.d[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hh, yo, prm.band_pitch, prm.nqx), oo);
+                for (int r = 0; r < ROWS; ++r) {
+                    q.a[r][0] = src[clamp_to(qy0 + r, py0, ph) * pw + xl];
+                    q.b[r][0] = load_elem<TB>(row_at<TB>(prm.hl, rb, prm.nqx), oo);
+                    q.c[r][0] = load_elem<TB>(row_at<TB>(prm.lh, rb, prm.nqx), oe);
+                    q.d[r][0] = load_elem<TB>(row_at<TB>(prm.hh, rb, prm.nqx), oo);
+                    rb += prm.band_pitch;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    const int gy = qy0 + r;
+                    const int ye = mirror(2 * gy, prm.h) >> 1;
+                    const int yo = (mirror(2 * gy + 1, prm.h) - 1) >> 1;
+                    q.a[r][0] = src[clamp_to(ye, py0, ph) * pw + xl];
+                    q.b[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hl, ye, prm.band_pitch, prm.nqx), oo);
+                    q.c[r][0] = load_elem<TB>(row_rsrc<TB>(prm.lh, yo, prm.band_pitch, prm.nqx), oe);
+                    q.d[r][0] = load_elem<TB>(row_rsrc<TB>(prm.hh, yo, prm.band_pitch, prm.nqx), oo);
+                }
             }
         }
 #pragma unroll
@@ -226,13 +247,14 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
         const uint32_t oo = (qx >= g.ox0 && qx < g.ox1) ? 2u * (uint32_t)qx * sizeof(TOUT)
                                                         : kNoAccess;
         const bool comp_x = qx >= g.cx0 && qx < g.cx1;
+        int64_t ro = (int64_t)(2 * qy0) * prm.out_pitch;   // pixel row 2 gy
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+        for (int r = 0; r < ROWS; ++r, ro += 2 * prm.out_pitch) {
             const int gy = qy0 + r;
             if (last) {
                 if (gy >= g.oy0 && gy < g.oy1) {   // wavefront-uniform
-                    const rsrc_t r0 = row_rsrc<TOUT>(prm.out, 2 * gy, prm.out_pitch, prm.w);
-                    const rsrc_t r1 = row_rsrc<TOUT>(prm.out, 2 * gy + 1, prm.out_pitch, prm.w);
+                    const rsrc_t r0 = row_at<TOUT>(prm.out, ro, prm.w);
+                    const rsrc_t r1 = row_at<TOUT>(prm.out, ro + prm.out_pitch, prm.w);
                     if (prm.vec_out) {
                         const float e[2] = {q.a[r][0], q.b[r][0]};
                         const float o[2] = {q.c[r][0], q.d[r][0]};
