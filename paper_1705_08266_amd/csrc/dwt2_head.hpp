@@ -148,15 +148,15 @@ __device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
         TB *hh = static_cast<TB *>(p1.hh);
         const uint32_t bb = (uint32_t)p1.nqx * (uint32_t)sizeof(TB);
         const uint32_t off = own_x ? (uint32_t)qx * (uint32_t)sizeof(TB) : kNoAccess;
+        int64_t rowo = (int64_t)qy0 * p1.band_pitch;   // band row qy0 + r, stepped
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+        for (int r = 0; r < ROWS; ++r, rowo += p1.band_pitch) {
             const int wr = wave * ROWS + r;
             const int gy = qy0 + r;
             if (wr < 3 * RG || wr >= 3 * RG + 2 * G::FOY2 || gy >= p1.nqy) continue;
             const float vb[2] = {q.b[r][0] * sHL, q.b[r][1] * sHL};
             const float vc[2] = {q.c[r][0] * sHL, q.c[r][1] * sHL};
             const float vd[2] = {q.d[r][0] * sHH, q.d[r][1] * sHH};
-            const int64_t rowo = (int64_t)gy * p1.band_pitch;
             if (p1.vec_band) {
                 store_vec<TB, 2>(make_rsrc(hl + rowo, bb), off, vb);
                 store_vec<TB, 2>(make_rsrc(lh + rowo, bb), off, vc);
@@ -203,15 +203,17 @@ __device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
     const bool own_x = lane >= RG && lane < RG + G::FOX2 && X < p2.nqx;
     const uint32_t ob = own_x ? (uint32_t)X * (uint32_t)sizeof(TB) : kNoAccess;
     const uint32_t ol = own_x ? (uint32_t)X * (uint32_t)sizeof(TLL) : kNoAccess;
+    int64_t rb = (int64_t)(r0 + wave * R2) * p2.band_pitch;   // row r0 + wr, stepped
+    int64_t rl = (int64_t)(r0 + wave * R2) * p2.ll_pitch;
 #pragma unroll
-    for (int r = 0; r < R2; ++r) {
+    for (int r = 0; r < R2; ++r, rb += p2.band_pitch, rl += p2.ll_pitch) {
         const int wr = wave * R2 + r;
         const int gy = r0 + wr;
         if (wr < RG || wr >= RG + G::FOY2 || gy >= p2.nqy) continue;   // wavefront-uniform
-        store_elem<TB>(row_rsrc<TB>(p2.hl, gy, p2.band_pitch, p2.nqx), ob, q.b[r][0] * sHL);
-        store_elem<TB>(row_rsrc<TB>(p2.lh, gy, p2.band_pitch, p2.nqx), ob, q.c[r][0] * sHL);
-        store_elem<TB>(row_rsrc<TB>(p2.hh, gy, p2.band_pitch, p2.nqx), ob, q.d[r][0] * sHH);
-        store_elem<TLL>(row_rsrc<TLL>(p2.ll, gy, p2.ll_pitch, p2.nqx), ol, q.a[r][0] * sLL);
+        store_elem<TB>(row_at<TB>(p2.hl, rb, p2.nqx), ob, q.b[r][0] * sHL);
+        store_elem<TB>(row_at<TB>(p2.lh, rb, p2.nqx), ob, q.c[r][0] * sHL);
+        store_elem<TB>(row_at<TB>(p2.hh, rb, p2.nqx), ob, q.d[r][0] * sHH);
+        store_elem<TLL>(row_at<TLL>(p2.ll, rl, p2.nqx), ol, q.a[r][0] * sLL);
     }
 }
 
@@ -300,14 +302,15 @@ __device__ __forceinline__ void inv_head_tile(const InvHead &hd, const int t,
     const int px0 = 2 * qx;
     const bool full_x = own_x && p1.vec_out && px0 + 4 <= p1.w;
     const uint32_t rb = (uint32_t)p1.w * (uint32_t)sizeof(TOUT);
+    int64_t ro = (int64_t)(2 * qy0) * p1.out_pitch;   // pixel row 2 (qy0 + r), stepped
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
+    for (int r = 0; r < ROWS; ++r, ro += 2 * p1.out_pitch) {
         const int wr = wave * ROWS + r;
         const int gy = qy0 + r;
         if (wr < RG || wr >= RG + G::IOY1 || gy >= p1.nqy) continue;   // wavefront-uniform
         const float e[4] = {q.a[r][0], q.b[r][0], q.a[r][1], q.b[r][1]};
         const float o[4] = {q.c[r][0], q.d[r][0], q.c[r][1], q.d[r][1]};
-        TOUT *r0p = out + (int64_t)(2 * gy) * p1.out_pitch;
+        TOUT *r0p = out + ro;
         TOUT *r1p = r0p + p1.out_pitch;
         if (p1.vec_out) {
             const uint32_t off = full_x ? (uint32_t)px0 * (uint32_t)sizeof(TOUT) : kNoAccess;

@@ -226,8 +226,10 @@ __device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdPa
     TB *lh = static_cast<TB *>(prm.lh);
     TB *hh = static_cast<TB *>(prm.hh);
     const bool full_x = qx0 + QPL <= prm.nqx;
+    // element offsets of row qy0 + r, stepped
+    int64_t rowb = (int64_t)qy0 * prm.band_pitch, rowl = (int64_t)qy0 * prm.ll_pitch;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
+    for (int r = 0; r < ROWS; ++r, rowb += prm.band_pitch, rowl += prm.ll_pitch) {
         const int wr = wave * ROWS + r;
         const int gy = qy0 + r;
         if (wr < G::HY || wr >= WAVES * ROWS - G::HY || gy >= prm.nqy) continue;
@@ -237,11 +239,10 @@ __device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdPa
             va[i] = q.a[r][i] * sLL; vb[i] = q.b[r][i] * sHL;
             vc[i] = q.c[r][i] * sHL; vd[i] = q.d[r][i] * sHH;
         }
-        const int64_t ob = (int64_t)gy * prm.band_pitch + qx0;
-        const int64_t ol = (int64_t)gy * prm.ll_pitch + qx0;
+        const int64_t ob = rowb + qx0;
+        const int64_t ol = rowl + qx0;
         if (full_x && prm.vec_ll) {
-            store_vec<TLL, QPL>(make_rsrc(ll + (int64_t)gy * prm.ll_pitch,
-                                          (uint32_t)prm.nqx * (uint32_t)sizeof(TLL)),
+            store_vec<TLL, QPL>(make_rsrc(ll + rowl, (uint32_t)prm.nqx * (uint32_t)sizeof(TLL)),
                                 (uint32_t)qx0 * (uint32_t)sizeof(TLL), va);
         } else {
 #pragma unroll
@@ -251,7 +252,7 @@ __device__ __forceinline__ void fwd_store(const Quads<ROWS, QPL> &q, const FwdPa
         if (full_x && prm.vec_band) {
             const uint32_t bb = (uint32_t)prm.nqx * (uint32_t)sizeof(TB);
             const uint32_t off = (uint32_t)qx0 * (uint32_t)sizeof(TB);
-            const int64_t rowo = (int64_t)gy * prm.band_pitch;
+            const int64_t rowo = rowb;
             store_vec<TB, QPL>(make_rsrc(hl + rowo, bb), off, vb);
             store_vec<TB, QPL>(make_rsrc(lh + rowo, bb), off, vc);
             store_vec<TB, QPL>(make_rsrc(hh + rowo, bb), off, vd);
@@ -398,8 +399,9 @@ __device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvPa
     TOUT *out = static_cast<TOUT *>(prm.out);
     const int px0 = 2 * qx0;
     const bool full_x = prm.vec_out && px0 + 2 * QPL <= prm.w;
+    int64_t ro = (int64_t)(2 * qy0) * prm.out_pitch;   // pixel row 2 (qy0 + r), stepped
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
+    for (int r = 0; r < ROWS; ++r, ro += 2 * prm.out_pitch) {
         const int wr = wave * ROWS + r;
         const int gy = qy0 + r;
         if (wr < G::HY || wr >= WAVES * ROWS - G::HY || gy >= prm.nqy) continue;
@@ -409,7 +411,7 @@ __device__ __forceinline__ void inv_store(const Quads<ROWS, QPL> &q, const InvPa
             e[2 * i] = q.a[r][i]; e[2 * i + 1] = q.b[r][i];
             o[2 * i] = q.c[r][i]; o[2 * i + 1] = q.d[r][i];
         }
-        TOUT *r0 = out + (int64_t)(2 * gy) * prm.out_pitch;
+        TOUT *r0 = out + ro;
         TOUT *r1 = r0 + prm.out_pitch;
         if (full_x) {
             const uint32_t rb = (uint32_t)prm.w * (uint32_t)sizeof(TOUT);
