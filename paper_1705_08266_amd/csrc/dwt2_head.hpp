@@ -185,16 +185,29 @@ __device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
     const int xe = mirror(2 * X, p2.w), xo = mirror(2 * X + 1, p2.w);
     const int ce = lds_at(xe >> 1, c0, 62), co = lds_at(xo >> 1, c0, 62);
     Quads<R2, 1> q;
+    const int Y0 = r0 + wave * R2;
+    if (Y0 >= 0 && 2 * (Y0 + R2) <= p2.h) {
+        // all rows inside the level (wavefront-uniform): no row is mirrored
 #pragma unroll
-    for (int r = 0; r < R2; ++r) {
-        const int Y = r0 + wave * R2 + r;
-        const int ye = mirror(2 * Y, p2.h), yo = mirror(2 * Y + 1, p2.h);
-        const int re = lds_at(ye >> 1, r0, H2), ro = lds_at(yo >> 1, r0, H2);
-        const int pe = 2 * (ye & 1), po = 2 * (yo & 1);
-        q.a[r][0] = ll1[pe + (xe & 1)][re][ce];
-        q.b[r][0] = ll1[pe + (xo & 1)][re][co];
-        q.c[r][0] = ll1[po + (xe & 1)][ro][ce];
-        q.d[r][0] = ll1[po + (xo & 1)][ro][co];
+        for (int r = 0; r < R2; ++r) {
+            const int ry = lds_at(Y0 + r, r0, H2);
+            q.a[r][0] = ll1[xe & 1][ry][ce];
+            q.b[r][0] = ll1[xo & 1][ry][co];
+            q.c[r][0] = ll1[2 + (xe & 1)][ry][ce];
+            q.d[r][0] = ll1[2 + (xo & 1)][ry][co];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+            const int Y = Y0 + r;
+            const int ye = mirror(2 * Y, p2.h), yo = mirror(2 * Y + 1, p2.h);
+            const int re = lds_at(ye >> 1, r0, H2), ro = lds_at(yo >> 1, r0, H2);
+            const int pe = 2 * (ye & 1), po = 2 * (yo & 1);
+            q.a[r][0] = ll1[pe + (xe & 1)][re][ce];
+            q.b[r][0] = ll1[pe + (xo & 1)][re][co];
+            q.c[r][0] = ll1[po + (xe & 1)][ro][ce];
+            q.d[r][0] = ll1[po + (xo & 1)][ro][co];
+        }
     }
     {
         Exchange<R2, 1, WAVES> x{reinterpret_cast<Mailbox<1, WAVES> *>(&box), wave, lane, 0};
@@ -277,13 +290,26 @@ __device__ __forceinline__ void inv_head_tile(const InvHead &hd, const int t,
             cx[i] = lds_at(xe >> 1, c0, 64);
             px[i] = xe & 1;
         }
+        if (qy0 >= 0 && 2 * (qy0 + ROWS) <= p1.h) {
+            // all rows inside the level (wavefront-uniform): quad row gy's low
+            // phase is row gy of the coarser output
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int ye = mirror(2 * (qy0 + r), p1.h) >> 1;
-            const int ry = lds_at(ye >> 1, r0, H2);
-            const int py = 2 * (ye & 1);
+            for (int r = 0; r < ROWS; ++r) {
+                const int gy = qy0 + r;
+                const int ry = lds_at(gy >> 1, r0, H2);
+                const int py = 2 * (gy & 1);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) q.a[r][i] = ll1[py + px[i]][ry][cx[i]];
+                for (int i = 0; i < 2; ++i) q.a[r][i] = ll1[py + px[i]][ry][cx[i]];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int ye = mirror(2 * (qy0 + r), p1.h) >> 1;
+                const int ry = lds_at(ye >> 1, r0, H2);
+                const int py = 2 * (ye & 1);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) q.a[r][i] = ll1[py + px[i]][ry][cx[i]];
+            }
         }
     }
 #pragma unroll
