@@ -138,10 +138,12 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
             const float *src = llbuf[(m - 1) & 1];
             const int xe = clamp_to(mirror(2 * qx, prm.w), px0, pw);
             const int xo = clamp_to(mirror(2 * qx + 1, prm.w), px0, pw);
+            const bool inside = qy0 >= 0 && 2 * (qy0 + ROWS) <= prm.h;   // wavefront-uniform
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
-                const int ye = clamp_to(mirror(2 * (qy0 + r), prm.h), py0, ph) * pw;
-                const int yo = clamp_to(mirror(2 * (qy0 + r) + 1, prm.h), py0, ph) * pw;
+                const int y = 2 * (qy0 + r);
+                const int ye = clamp_to(inside ? y : mirror(y, prm.h), py0, ph) * pw;
+                const int yo = clamp_to(inside ? y + 1 : mirror(y + 1, prm.h), py0, ph) * pw;
                 q.a[r][0] = src[ye + xe]; q.b[r][0] = src[ye + xo];
                 q.c[r][0] = src[yo + xe]; q.d[r][0] = src[yo + xo];
             }
