@@ -72,13 +72,13 @@ __device__ __forceinline__ int lds_at(int p, int p0, int n) { return min(max(p -
 
 // Wavefronts per SIMD that the register allocation must allow. Two head
 // workgroups share a CU (their LDS fits twice), which takes WAVES/2 per SIMD,
-// i.e. at most 80 VGPRs for 12 wavefronts. Left free, the separable forward
-// head with 16-bit input comes out at 81 and runs one workgroup per CU (about
-// 35% slower); that instantiation is held to the budget. The others fit as they
-// are and keep the allocation the workgroup size alone implies.
+// i.e. at most 80 VGPRs for 12 wavefronts. Left free, forward heads with
+// 16-bit input come out at 80-81 (the separable FP16 one and the BF16 ones at
+// 81) and then run one workgroup per CU (about 35% slower); those
+// instantiations are held to the budget. The FP32 ones fit as they are and
+// keep the allocation the workgroup size alone implies.
 template <int SCH, int WAVES, typename TIN>
-constexpr int kFwdHeadWavesPerSimd =
-    (SCH == SEP && sizeof(TIN) == 2) ? (2 * WAVES + 3) / 4 : (WAVES + 3) / 4;
+constexpr int kFwdHeadWavesPerSimd = sizeof(TIN) == 2 ? (2 * WAVES + 3) / 4 : (WAVES + 3) / 4;
 template <int WAVES>
 constexpr int kInvHeadWavesPerSimd = (WAVES + 3) / 4;
 // The batched heads (which read their parameters from the plan, one more
@@ -141,7 +141,10 @@ __device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
                 }
             }
         }
-        // detail bands of the quads under the owned level j+1 block
+        __syncthreads();   // the low-low band is in LDS; every level j exchange is done
+        // detail bands of the quads under the owned level j+1 block, issued
+        // after the barrier so that no wavefront waits there for another's
+        // store addressing
         const bool own_x = lane >= RG + 1 && lane < RG + 1 + G::FOX2 && qx + 2 <= p1.nqx;
         TB *hl = static_cast<TB *>(p1.hl);
         TB *lh = static_cast<TB *>(p1.lh);
@@ -172,7 +175,6 @@ __device__ __forceinline__ void fwd_head_tile(const FwdHead &hd, const int t,
             }
         }
     }
-    __syncthreads();   // the low-low band is in LDS; every level j exchange is done
 
     // ---- level j+1: window of 62 x H2 quads, one per lane, R2 rows per wavefront
     const FwdParams &p2 = hd.l2;
