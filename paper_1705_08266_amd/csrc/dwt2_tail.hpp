@@ -112,7 +112,10 @@ __global__ __launch_bounds__(64 * kTailWaves) void fwd_tail_kernel(FwdTail t) {
     __shared__ float llbuf[2][kTailBuf];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bx = blockIdx.x % t.blocks_x, by = blockIdx.x / t.blocks_x;
+    // XCD-contiguous block numbering: neighbouring blocks, whose halo
+    // pyramids overlap, run on the same XCD and share its L2
+    const int blk = block_tile();
+    const int bx = blk % t.blocks_x, by = blk / t.blocks_x;
     const float sLL = (float)(L::ZL * L::ZL), sHL = (float)(L::ZL * L::ZH);
     const float sHH = (float)(L::ZH * L::ZH);
     int px0 = 0, py0 = 0, pw = 1, ph = 1;       // previous level's LL region in LDS
@@ -185,7 +188,10 @@ __global__ __launch_bounds__(64 * kTailWaves) void inv_tail_kernel(InvTail t) {
     __shared__ float pxbuf[2][kTailBuf];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bx = blockIdx.x % t.blocks_x, by = blockIdx.x / t.blocks_x;
+    // XCD-contiguous block numbering: neighbouring blocks, whose halo
+    // pyramids overlap, run on the same XCD and share its L2
+    const int blk = block_tile();
+    const int bx = blk % t.blocks_x, by = blk / t.blocks_x;
     const float uLL = (float)(1.0 / (L::ZL * L::ZL)), uHL = (float)(1.0 / (L::ZL * L::ZH));
     const float uHH = (float)(1.0 / (L::ZH * L::ZH));
     int px0 = 0, py0 = 0, pw = 1, ph = 1;       // previous level's output region in LDS
