@@ -696,6 +696,98 @@ def run_serve_workload(args):
         saturation=sat, latency_sweep=sweep, small_budget=small)), flush=True)
 
 
+def run_ab_workload(args):
+    """Two builds of the library in one process: the package's libdwt2.so (A)
+    and --other-lib (B), each loaded through its C ABI, alternate in rounds of
+    forward+inverse steps on the same buffers (order swapped every round),
+    after a check that both give the same bits. For design choices whose
+    effect is smaller than the spread between GPUs of the same kind."""
+    import ctypes
+    import statistics
+    import torch
+    from paper_1705_08266_amd import _lib
+
+    if not args.other_lib:
+        print("--workload ab needs --other-lib PATH (another build of libdwt2.so)", file=sys.stderr)
+        sys.exit(2)
+
+    def load(path):
+        lib = ctypes.CDLL(path, mode=ctypes.RTLD_LOCAL)
+        for f in (lib.dwt2_forward, lib.dwt2_inverse):
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_void_p, ctypes.POINTER(_lib.Desc), ctypes.c_void_p,
+                          ctypes.POINTER(_lib.Desc), ctypes.c_int, ctypes.c_int32, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.dwt2_workspace_bytes.restype = ctypes.c_size_t
+        lib.dwt2_workspace_bytes.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int]
+        return lib
+
+    paths = [_lib.LIB_PATH, os.path.abspath(args.other_lib)]
+    libs = [load(p) for p in paths]
+    W, H = (int(v) for v in args.size.lower().split("x"))
+    L = args.levels
+    code = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[args.dtype]
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    wav = 0 if args.wavelet == "cdf97" else 1
+    sch = 0 if args.scheme == "nonseparable" else 1
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(0)
+    x = (torch.rand(H, W, device=dev, generator=gen) * 255).to(tdt)
+    wsb = int(libs[0].dwt2_workspace_bytes(W, H, L, code))
+    sets = [(x.clone(), torch.empty_like(x), torch.empty_like(x),
+             torch.empty(wsb // 4 + 1, device=dev)) for _ in range(buffer_sets(args, W, H))]
+    d = _lib.Desc(W, H, W, code)
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def step(lib, k):
+        src, coef, rec, ws = sets[k % len(sets)]
+        for st in (lib.dwt2_forward(src.data_ptr(), ctypes.byref(d), coef.data_ptr(),
+                                    ctypes.byref(d), wav, L, 0, sch, ws.data_ptr(), wsb, sp),
+                   lib.dwt2_inverse(coef.data_ptr(), ctypes.byref(d), rec.data_ptr(),
+                                    ctypes.byref(d), wav, L, 0, sch, ws.data_ptr(), wsb, sp)):
+            if st != 0:
+                raise RuntimeError(f"library call failed with status {st}")
+
+    outs = []
+    for lib in libs:
+        step(lib, 0)
+        torch.cuda.synchronize()
+        outs.append((sets[0][1].clone(), sets[0][2].clone()))
+    same = bool(torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]))
+    rounds, per = 30, max(1, args.steps // 10)
+    us = [[], []]
+    for rnd in range(rounds):
+        for i in ((0, 1) if rnd % 2 == 0 else (1, 0)):
+            for k in range(len(sets)):
+                step(libs[i], k)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            for k in range(per):
+                step(libs[i], k)
+            b.record()
+            torch.cuda.synchronize()
+            us[i].append(a.elapsed_time(b) / per * 1e3)
+
+    def spread(v):
+        v = sorted(v)
+        return dict(median=round(statistics.median(v), 3), p10=round(v[len(v) // 10], 3),
+                    p90=round(v[9 * len(v) // 10], 3))
+    diff = [p - q for p, q in zip(us[0], us[1])]
+    med = statistics.median(us[0])
+    print(json.dumps(dict(
+        metric="us per forward+inverse step, two builds alternating in one process",
+        value=round(med, 3), unit="us", n_gpus=1, steps=rounds * per, warmup=len(sets),
+        ms_per_step=round(med / 1e3, 5), higher_is_better=False, scaling="weak",
+        vs_baseline=None, dtype=args.dtype, data="synthetic",
+        config=dict(workload=(f"{W}x{H} uniform image, {args.dtype} storage, {args.wavelet} "
+                              f"forward+inverse, {L} levels, {args.scheme} lifting, {rounds} "
+                              f"alternating rounds of {per} steps"),
+                    a=paths[0], b=paths[1]),
+        bit_identical=same, a_us=spread(us[0]), b_us=spread(us[1]),
+        a_minus_b_us=spread(diff))), flush=True)
+
+
 def serve_measure(args, n, dtype, fractions):
     """Serving runs of n requests drawn (seeded) from a pool of SERVE_POOL
     request shapes whose inputs are resident on the device and reused:
@@ -797,9 +889,12 @@ def main():
                     help="serving: two levels per step in fused head launches (on) or one")
     ap.add_argument("--fuse", default="auto", choices=["auto", "off"],
                     help="auto: the library fuses the coarse levels; off: one launch per level")
-    ap.add_argument("--workload", default="image", choices=["image", "batch", "serve"],
+    ap.add_argument("--workload", default="image", choices=["image", "batch", "serve", "ab"],
                     help="image: one image forward+inverse (headline); batch: many uneven "
-                         "images, batched forward")
+                         "images, batched forward; serve: continuous batching; ab: this build "
+                         "against --other-lib, alternating in one process")
+    ap.add_argument("--other-lib", default=None,
+                    help="ab workload: path of another build of libdwt2.so")
     ap.add_argument("--batch", type=int, default=256, help="images in the batch workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 4 device copies of 64 MiB (reference kernel of known "
@@ -816,6 +911,9 @@ def main():
         if args.levels == 5 and "--levels" not in sys.argv:
             args.levels = 3
         run_batch_workload(args)
+        return
+    if args.workload == "ab":
+        run_ab_workload(args)
         return
     if args.workload == "serve":
         if "--dtype" not in sys.argv:
