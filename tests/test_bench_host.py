@@ -116,3 +116,14 @@ def test_executed_bytes_with_fused_head(bench):
     # FP16 storage: the head writes 16-bit bands and an FP32 level-2 LL
     lb16 = bench.level_bytes(W, H, 5, 2)
     assert bench.unit_bytes(W, H, 5, 2, ("head", 1, 2)) == lb16[0] + lb16[1] - 2 * 4 * 2048 * 2048
+
+
+def test_ab_workload_needs_the_other_build():
+    """The two-build comparison refuses to run without the second library,
+    before touching a GPU."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "ab"],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120,
+                       cwd=ROOT)
+    assert r.returncode == 2
+    assert "--other-lib" in r.stderr
+    assert r.stdout == ""
