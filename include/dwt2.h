@@ -169,7 +169,7 @@ int dwt2_forward_no_alloc(const void *src, const dwt2_desc *src_d, void *coef,
 /* Tile id that marks levels 1 and 2 as one fused launch (the "head"). */
 #define DWT2_TILE_HEAD (-3)
 #define DWT2_TAIL_MAX 3
-#define DWT2_TAIL_AUTO_PIXELS (1 << 20)
+#define DWT2_TAIL_AUTO_PIXELS (1 << 22)
 
 /* Number of trailing levels that dwt2_forward and dwt2_inverse fuse into
  * one launch (0 when none; never 1). Multi-scale fusion is the paper's

@@ -19,7 +19,7 @@ NONSEPARABLE, SEPARABLE, NONSEPARABLE_LDS, SEPARABLE_LDS = 0, 1, 2, 3
 TILE_TAIL = -2            # tiles[j] of a level that runs in the fused tail launch
 TILE_HEAD = -3            # tiles[0] and tiles[1]: levels 1 and 2 in one fused launch
 TAIL_MAX = 3
-TAIL_AUTO_PIXELS = 1 << 20
+TAIL_AUTO_PIXELS = 1 << 22
 STATIC_WORKSPACE_BYTES = 64 << 20   # DWT2_STATIC_WORKSPACE_BYTES
 
 # Every function declared in include/dwt2.h: name -> (restype, argtypes)

@@ -175,9 +175,11 @@ def test_fused_tail_tile_ids():
     assert _fwd(levels=3, tiles=tiles(T, T, T)) == W
     assert _lib.TAIL_MAX == 3
     import paper_1705_08266_amd as dwt
-    assert dwt.fused_levels(4096, 4096, 5) == 3            # levels 3..5 (1024^2 and below)
-    assert dwt.fused_levels(7680, 4320, 5) == 2            # levels 4..5
-    assert dwt.fused_levels(16384, 16384, 5) == 0          # only level 5 is small
+    assert dwt.fused_levels(4096, 4096, 5) == 3            # levels 3..5 (at most 3 fused)
+    assert dwt.fused_levels(7680, 4320, 5) == 3            # levels 3..5 (1920x1080 and below)
+    assert dwt.fused_levels(8192, 8192, 5) == 3            # levels 3..5 (2048^2 and below)
+    assert dwt.fused_levels(16384, 16384, 5) == 2          # levels 4..5
+    assert dwt.fused_levels(16384, 16384, 3) == 0          # level 3 alone is not fused
     assert dwt.fused_levels(512, 512, 1) == 0
     assert dwt.fused_levels(256, 384, 3) == 3
     assert _lib.load().dwt2_fused_levels(64, 64, 7) == _lib.ERR_INVALID_ARG
